@@ -1,0 +1,324 @@
+// Right-hand-side blocks for the paper's three ways of computing farness and
+// the reductions that turn block solutions into resistances and farness:
+//   exact     -- n-1 systems L p = e_v - e_w per node (Sec. 4, Eq. 3);
+//   Sampling  -- k pivots per node, (n/k) sum of d_ER(v, s) (Sec. 5.1);
+//   projection -- k systems L z_i = (Q W^(1/2) B)_i (Sec. 5.2, Algorithm 1).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "kern.hpp"
+#include "solver.hpp"
+
+namespace cfc {
+
+cfc_solve_params default_solve() {
+  cfc_solve_params p;
+  p.tol = 1e-6;
+  p.precision = CFC_PREC_MIXED;
+  p.block = 0;
+  p.max_refine = 20;
+  p.max_inner = 300;
+  p.inner_tol = 1e-4;
+  p.use_graph = 0;
+  p.check_every = 1;
+  return p;
+}
+
+static bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+static void check_params(const cfc_solve_params& p) {
+  if (!(p.tol > 0 && p.tol < 1)) fail(CFC_E_INVALID, "tol must be in (0, 1)");
+  if (p.precision != CFC_PREC_MIXED && p.precision != CFC_PREC_FP64) fail(CFC_E_INVALID, "bad precision");
+  if (p.max_refine < 0 || p.max_inner < 1) fail(CFC_E_INVALID, "bad iteration limits");
+  if (!(p.inner_tol > 0 && p.inner_tol < 1)) fail(CFC_E_INVALID, "inner_tol must be in (0, 1)");
+  if (p.block != 0 && !kern_table(p.block, false)) fail(CFC_E_INVALID, "block must be 0, 1, 32, 64, 128, 256 or 512");
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time a short solve per candidate width, keep the cheapest time
+// per column-iteration; cached in the graph and optionally on disk
+// (CFC_TUNE_CACHE names a text file of "n nnz levels precision W" lines).
+
+static std::string tune_key(const Graph& g, int prec) {
+  std::ostringstream o;
+  o << g.n << ' ' << g.col.size() << ' ' << g.H.lv.size() << ' ' << prec;
+  return o.str();
+}
+
+int choose_block(Graph& g, const cfc_solve_params& p0, int64_t ncols) {
+  if (p0.block) return p0.block;
+  const int prec = p0.precision;
+  if (g.tuned_W && (g.tuned_W >> 16) == prec + 1) return g.tuned_W & 0xffff;
+  const char* cache = std::getenv("CFC_TUNE_CACHE");
+  const std::string key = tune_key(g, prec);
+  if (cache) {
+    std::ifstream f(cache);
+    std::string line;
+    while (std::getline(f, line)) {
+      if (line.rfind(key + " ", 0) == 0) {
+        int W = std::atoi(line.c_str() + key.size() + 1);
+        if (kern_table(W, false)) {
+          g.tuned_W = ((prec + 1) << 16) | W;
+          return W;
+        }
+      }
+    }
+  }
+  std::vector<int> cand = prec == CFC_PREC_FP64 ? std::vector<int>{64, 128, 256}
+                                                : std::vector<int>{64, 128, 256, 512};
+  const double n0 = (double)g.n;
+  const double es = prec == CFC_PREC_FP64 ? 8 : 4;
+  double best_t = 1e300;
+  int best = 256;
+  const uint64_t budget = g.ctx->budget;
+  for (int W : cand) {
+    if (ncols > 0 && W > 64 && W / 2 >= ncols) break;  // would leave most columns idle
+    const double need = n0 * W * (6 * es + 16) * 1.6;
+    if (budget && g.ctx->in_use + need > budget) break;
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > 0.8 * (double)freeb) break;
+    cfc_solve_params p = p0;
+    p.block = W;
+    p.max_refine = 1;
+    p.max_inner = 4;
+    p.check_every = 1000;
+    p.inner_tol = 1e-12;
+    std::vector<int64_t> s(W), t(W);
+    for (int j = 0; j < W; ++j) {
+      s[j] = (int64_t)((uint64_t(j) * 2654435761ull) % uint64_t(g.n));
+      t[j] = (int64_t)((uint64_t(j) * 40503ull + 17) % uint64_t(g.n));
+    }
+    std::vector<double> out(W);
+    double tm = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {  // first run allocates and warms up
+      cfc_solve_stats st{};
+      pair_solves(g, W, s.data(), t.data(), out.data(), p, &st, nullptr);
+      const double its = std::max<int64_t>(1, st.inner_iters) + 2.0;
+      tm = st.solve_ms / (its * W);
+    }
+    if (tm < best_t) { best_t = tm; best = W; }
+  }
+  // release workspaces of the losing widths
+  g.ws.erase(std::remove_if(g.ws.begin(), g.ws.end(),
+                            [&](const std::unique_ptr<Workspace>& w) { return w->W != best; }),
+             g.ws.end());
+  g.tuned_W = ((prec + 1) << 16) | best;
+  if (cache) {
+    std::ofstream f(cache, std::ios::app);
+    f << key << ' ' << best << '\n';
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+
+void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_solve_params& p0,
+                 cfc_solve_stats* st, int32_t* col_status) {
+  check_params(p0);
+  if (nrhs < 0 || (nrhs > 0 && (!B || !X))) fail(CFC_E_INVALID, "bad B/X");
+  const int64_t n = g.n;
+  std::vector<double> hB;
+  const double* Bh = B;
+  const bool bdev = is_device_ptr(B), xdev = is_device_ptr(X);
+  if (bdev) {
+    hB.resize((size_t)n * nrhs);
+    CFC_HIP(hipMemcpy(hB.data(), B, hB.size() * sizeof(double), hipMemcpyDeviceToHost));
+    Bh = hB.data();
+  }
+  for (int64_t j = 0; j < nrhs; ++j) {
+    double s = 0, a = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double v = Bh[j * n + i];
+      if (!std::isfinite(v)) fail(CFC_E_INVALID, "B column " + std::to_string(j) + " is not finite");
+      s += v;
+      a += std::fabs(v);
+    }
+    if (std::fabs(s) > 1e-12 * a + 1e-300 && a > 0)
+      fail(CFC_E_INVALID, "B column " + std::to_string(j) + " does not sum to zero");
+  }
+  cfc_solve_params p = p0;
+  p.block = choose_block(g, p0, nrhs);
+  Solver S(g, p);
+  Workspace& w = *S.ws;
+  const int W = w.W;
+  if (!w.rhs.p) w.rhs.alloc(g.ctx, (size_t)n * W * sizeof(double));
+  std::vector<double> blk((size_t)n * W), xo((size_t)n * W), hX;
+  double* Xh = X;
+  if (xdev) {
+    hX.resize((size_t)n * nrhs);
+    Xh = hX.data();
+  }
+  const std::vector<int32_t>& perm = g.H.perm;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += W) {
+    const int nc = (int)std::min<int64_t>(W, nrhs - c0);
+    std::fill(blk.begin(), blk.end(), 0.0);
+    for (int j = 0; j < nc; ++j) {
+      const double* col = Bh + (c0 + j) * n;
+      for (int64_t i = 0; i < n; ++i) blk[(size_t)perm[i] * W + j] = col[i];
+    }
+    CFC_HIP(hipMemcpyAsync(w.rhs.p, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice,
+                           S.stream));
+    RhsArgs r;
+    r.kind = 0;
+    r.dense = w.rhs.as<double>();
+    S.solve_block(r, nc, p, col_status ? col_status + c0 : nullptr, nullptr);
+    CFC_HIP(hipMemcpyAsync(xo.data(), w.x64.p, xo.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           S.stream));
+    CFC_HIP(hipStreamSynchronize(S.stream));
+    for (int j = 0; j < nc; ++j) {
+      double* col = Xh + (c0 + j) * n;
+      double m = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        col[i] = xo[(size_t)perm[i] * W + j];
+        m += col[i];
+      }
+      m /= double(n);  // exact FP64 projection of the returned copy
+      for (int64_t i = 0; i < n; ++i) col[i] -= m;
+    }
+  }
+  S.finish(st);
+  if (xdev) CFC_HIP(hipMemcpy(X, hX.data(), hX.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (S.converged < S.columns) fail(CFC_E_NOT_CONVERGED, "some columns missed the tolerance");
+}
+
+void pair_solves(Graph& g, int64_t npairs, const int64_t* s, const int64_t* t, double* out,
+                 const cfc_solve_params& p0, cfc_solve_stats* st, int32_t* col_status) {
+  check_params(p0);
+  for (int64_t j = 0; j < npairs; ++j)
+    if (s[j] < 0 || s[j] >= g.n || t[j] < 0 || t[j] >= g.n) fail(CFC_E_INVALID, "node id out of range");
+  cfc_solve_params p = p0;
+  p.block = choose_block(g, p0, npairs);
+  Solver S(g, p);
+  Workspace& w = *S.ws;
+  const int W = w.W;
+  int* ps = w.pairs.as<int>();
+  int* pt = ps + W;
+  double* dd = w.dvec.as<double>();
+  std::vector<int> hp(2 * W);
+  std::vector<double> res(W);
+  std::vector<int32_t> stat(W);
+  for (int64_t c0 = 0; c0 < npairs; c0 += W) {
+    const int nc = (int)std::min<int64_t>(W, npairs - c0);
+    for (int j = 0; j < W; ++j) {
+      if (j < nc) {
+        hp[j] = g.H.perm[s[c0 + j]];
+        hp[W + j] = g.H.perm[t[c0 + j]];
+        if (hp[j] == hp[W + j]) hp[j] = hp[W + j] = -1;  // e_v - e_v = 0
+      } else {
+        hp[j] = hp[W + j] = -1;
+      }
+    }
+    CFC_HIP(hipMemcpyAsync(ps, hp.data(), 2 * W * sizeof(int), hipMemcpyHostToDevice, S.stream));
+    RhsArgs r;
+    r.kind = 1;
+    r.ps = ps;
+    r.pt = pt;
+    S.solve_block(r, nc, p, stat.data(), nullptr);
+    pair_diff(W, nc, w.x64.as<double>(), ps, pt, dd, S.stream);
+    CFC_HIP(hipMemcpyAsync(res.data(), dd, nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
+    CFC_HIP(hipStreamSynchronize(S.stream));
+    for (int j = 0; j < nc; ++j) {
+      out[c0 + j] = res[j];
+      if (col_status) col_status[c0 + j] = stat[j];
+    }
+  }
+  S.finish(st);
+}
+
+// ---------------------------------------------------------------------------
+// projection estimator
+
+void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p0, cfc_solve_stats* st) {
+  check_params(p0);
+  if (k < 1) fail(CFC_E_INVALID, "k must be >= 1");
+  cfc_solve_params p = p0;
+  p.block = choose_block(g, p0, k);
+  g.jl.valid = false;
+  const int n0 = g.D->lv[0].n;
+  Solver S(g, p);
+  Workspace& w = *S.ws;
+  const int W = w.W;
+  if (!w.rhs.p) w.rhs.alloc(g.ctx, (size_t)n0 * W * sizeof(double));
+  if (g.jl.N_dev.bytes != (size_t)n0 * 8) {
+    g.jl.N_dev.alloc(g.ctx, (size_t)n0 * 8);
+    g.jl.T_dev.alloc(g.ctx, (size_t)n0 * 8);
+    g.jl.S2_dev.alloc(g.ctx, 1024 * 8 + 8);
+  }
+  w.kt->zero(g.jl.N_dev.p, g.jl.N_dev.bytes, S.stream);
+  w.kt->zero(g.jl.T_dev.p, g.jl.T_dev.bytes, S.stream);
+  LevelArgs l64 = w.la64;
+  const int grow = grid_for(n0, w.kt->rg);
+  std::vector<int32_t> stat(W);
+  for (int64_t i0 = 0; i0 < k; i0 += W) {
+    const int nc = (int)std::min<int64_t>(W, k - i0);
+    w.kt->jl_rhs(l64, g.D->iperm.as<int>(), seed, i0, k, w.rhs.as<double>(), S.stream);
+    S.bytes += (double)n0 * W * 8 + 4.0 * g.D->lv[0].nnz + 8.0 * n0;
+    RhsArgs r;
+    r.kind = 0;
+    r.dense = w.rhs.as<double>();
+    S.solve_block(r, nc, p, stat.data(), nullptr);
+    // per-node |Z_v|^2, column sums s, then Z_v . s
+    w.kt->jl_rownorm(n0, w.x64.as<double>(), nc, g.jl.N_dev.as<double>(), w.part_ptr(P_CS), S.stream);
+    finalize(W, F_CS, grow, w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(), S.stream);
+    w.kt->jl_rowdot(n0, w.x64.as<double>(), nc, w.scal.as<double>(), g.jl.T_dev.as<double>(), S.stream);
+    S.bytes += 2.0 * n0 * W * 8 + 4.0 * n0 * 8;
+  }
+  double* part = g.jl.S2_dev.as<double>() + 1;
+  reduce_sum(n0, g.jl.N_dev.as<double>(), part, g.jl.S2_dev.as<double>(), S.stream);
+  double S2 = 0;
+  CFC_HIP(hipMemcpyAsync(&S2, g.jl.S2_dev.p, 8, hipMemcpyDeviceToHost, S.stream));
+  CFC_HIP(hipStreamSynchronize(S.stream));
+  S.finish(st);
+  g.jl.k = k;
+  g.jl.seed = seed;
+  g.jl.S2 = S2;
+  g.jl.valid = S.converged == S.columns;
+  if (!g.jl.valid) fail(CFC_E_NOT_CONVERGED, "projection solves missed the tolerance");
+}
+
+void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* clo) {
+  if (!g.jl.valid) fail(CFC_E_STATE, "no projection sketch (call cfc_jl_sketch)");
+  if (q < 0 || (q > 0 && (!nodes || !far))) fail(CFC_E_INVALID, "bad arguments");
+  std::vector<int> idx(q);
+  for (int64_t i = 0; i < q; ++i) {
+    if (nodes[i] < 0 || nodes[i] >= g.n) fail(CFC_E_INVALID, "node id out of range");
+    idx[i] = g.H.perm[nodes[i]];
+  }
+  if (q == 0) return;
+  Ctx* c = g.ctx;
+  DBuf di, dn, dt;
+  di.alloc(c, q * sizeof(int));
+  dn.alloc(c, q * sizeof(double));
+  dt.alloc(c, q * sizeof(double));
+  hipStream_t s = c->stream;
+  CFC_HIP(hipMemcpyAsync(di.p, idx.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
+  gather((int)q, g.jl.N_dev.as<double>(), di.as<int>(), dn.as<double>(), s);
+  gather((int)q, g.jl.T_dev.as<double>(), di.as<int>(), dt.as<double>(), s);
+  std::vector<double> hn(q), ht(q);
+  CFC_HIP(hipMemcpyAsync(hn.data(), dn.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
+  CFC_HIP(hipMemcpyAsync(ht.data(), dt.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
+  CFC_HIP(hipStreamSynchronize(s));
+  const double n = (double)g.n;
+  for (int64_t i = 0; i < q; ++i) {
+    // sum_w |Z_v - Z_w|^2 = n |Z_v|^2 - 2 Z_v . sum_w Z_w + |Z|_F^2
+    const double f = n * hn[i] - 2.0 * ht[i] + g.jl.S2;
+    far[i] = f;
+    if (clo) clo[i] = f > 0 ? (n - 1) / f : INFINITY;
+  }
+}
+
+}  // namespace cfc

@@ -1,0 +1,357 @@
+// Multigrid hierarchy setup (host).
+//
+// The paper's solver builds coarser systems by aggregating nodes according to
+// an affinity measure (Sec. 3.1); its details are not given there, so the
+// design here is this library's own:
+//   * affinity of an edge {u,v}: c_uv = <X_u, X_v>^2 / (|X_u|^2 |X_v|^2) over
+//     K test vectors relaxed toward the near-null space of L;
+//   * greedy aggregation in ascending-degree order: each free node joins its
+//     strongest neighbour's aggregate (or founds one with a free neighbour)
+//     while the aggregate has fewer than `agg_cap` nodes; a node whose
+//     neighbours all sit in full aggregates joins an overflow aggregate keyed
+//     by its strongest neighbour's aggregate;
+//   * piecewise-constant interpolation P(u, I) = 1 iff u is in I and the
+//     Galerkin operator P^T L P, which is again a graph Laplacian: the quotient
+//     graph with W_IJ = sum of w_uv over u in I, v in J;
+//   * a nested renumbering that makes every aggregate a contiguous row range
+//     on every level (restriction and prolongation then need no atomics and
+//     neighbouring rows stay close in memory);
+//   * the coarsest level's dense pseudoinverse L_c^+ = Pi G Pi, with G the
+//     inverse of L_c grounded at node 0 (Sec. 4, last paragraph) padded with
+//     a zero row and column, and Pi = I - 11^T / n_c.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace cfc {
+
+cfc_setup_params default_setup() {
+  cfc_setup_params p;
+  p.coarsest_max = 512;
+  p.agg_cap = 8;
+  p.test_vectors = 8;
+  p.relax_sweeps = 8;
+  p.omega = 2.0 / 3.0;
+  p.mu = 1.5;
+  p.seed = 1;
+  return p;
+}
+
+namespace {
+
+struct BLevel {  // a level in build numbering
+  int64_t n = 0;
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> w, deg;
+  std::vector<int32_t> agg;  // to next level (build numbering)
+  int64_t nagg = 0;
+};
+
+constexpr uint64_t kTagTestVec = 0x5456ull;
+
+// Affinity-based greedy aggregation.  Returns the number of aggregates.
+int64_t aggregate(const BLevel& L, int level, const cfc_setup_params& p, std::vector<int32_t>& agg) {
+  const int64_t n = L.n;
+  const int K = std::max(1, p.test_vectors);
+  // test vectors, node-major n x K
+  std::vector<double> X(n * K), Y(n * K);
+  for (int64_t u = 0; u < n; ++u)
+    for (int k = 0; k < K; ++k) {
+      uint64_t h = key_hash(p.seed, kTagTestVec, uint64_t(level) * 1024 + k, uint64_t(u));
+      X[u * K + k] = double(h >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    }
+  const double om = 0.6;
+  for (int s = 0; s < p.relax_sweeps; ++s) {
+    for (int64_t u = 0; u < n; ++u) {
+      double acc[64];
+      for (int k = 0; k < K; ++k) acc[k] = L.deg[u] * X[u * K + k];
+      for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e) {
+        const double we = L.w[e];
+        const double* xv = &X[int64_t(L.col[e]) * K];
+        for (int k = 0; k < K; ++k) acc[k] -= we * xv[k];
+      }
+      const double sc = L.deg[u] > 0 ? om / L.deg[u] : 0.0;
+      for (int k = 0; k < K; ++k) Y[u * K + k] = X[u * K + k] - sc * acc[k];
+    }
+    X.swap(Y);
+  }
+  for (int k = 0; k < K; ++k) {  // remove the constant component
+    double s = 0;
+    for (int64_t u = 0; u < n; ++u) s += X[u * K + k];
+    s /= double(n);
+    for (int64_t u = 0; u < n; ++u) X[u * K + k] -= s;
+  }
+  std::vector<double> nx(n);
+  for (int64_t u = 0; u < n; ++u) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += X[u * K + k] * X[u * K + k];
+    nx[u] = s;
+  }
+  auto affinity = [&](int64_t u, int64_t v) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += X[u * K + k] * X[v * K + k];
+    double den = nx[u] * nx[v];
+    return den > 0 ? s * s / den : 0.0;
+  };
+  std::vector<int64_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return (L.rowptr[a + 1] - L.rowptr[a]) < (L.rowptr[b + 1] - L.rowptr[b]);
+  });
+  agg.assign(n, -1);
+  std::vector<int32_t> size;
+  std::vector<int32_t> overflow;  // aggregate -> its open overflow aggregate (-1)
+  const int cap = std::max(2, p.agg_cap);
+  for (int64_t u : order) {
+    if (agg[u] >= 0) continue;
+    int64_t best = -1, strongest = -1;
+    double bv = -1, sv = -1;
+    for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e) {
+      int64_t v = L.col[e];
+      double a = affinity(u, v) * (1.0 + 1e-12 * L.w[e]);
+      if (a > sv) { sv = a; strongest = v; }
+      if (agg[v] >= 0 && size[agg[v]] >= cap) continue;
+      if (a > bv) { bv = a; best = v; }
+    }
+    if (best >= 0) {
+      if (agg[best] < 0) {
+        int32_t id = (int32_t)size.size();
+        size.push_back(2);
+        overflow.push_back(-1);
+        agg[u] = agg[best] = id;
+      } else {
+        agg[u] = agg[best];
+        size[agg[best]]++;
+      }
+    } else if (strongest >= 0) {
+      int32_t A = agg[strongest];
+      int32_t o = overflow[A];
+      if (o >= 0 && size[o] < cap) {
+        agg[u] = o;
+        size[o]++;
+      } else {
+        int32_t id = (int32_t)size.size();
+        size.push_back(1);
+        overflow.push_back(-1);
+        overflow[A] = id;
+        agg[u] = id;
+      }
+    } else {  // isolated node (only when n == 1)
+      int32_t id = (int32_t)size.size();
+      size.push_back(1);
+      overflow.push_back(-1);
+      agg[u] = id;
+    }
+  }
+  return (int64_t)size.size();
+}
+
+// Galerkin quotient graph P^T L P for piecewise-constant P.
+BLevel galerkin(const BLevel& F, const std::vector<int32_t>& agg, int64_t nc) {
+  BLevel C;
+  C.n = nc;
+  std::vector<int32_t> start(nc + 1, 0), members(F.n);
+  for (int64_t u = 0; u < F.n; ++u) start[agg[u] + 1]++;
+  for (int64_t i = 0; i < nc; ++i) start[i + 1] += start[i];
+  {
+    std::vector<int32_t> pos(start.begin(), start.end() - 1);
+    for (int64_t u = 0; u < F.n; ++u) members[pos[agg[u]]++] = (int32_t)u;
+  }
+  std::vector<int32_t> mark(nc, -1);
+  std::vector<double> acc;
+  std::vector<int32_t> cols;
+  C.rowptr.assign(nc + 1, 0);
+  for (int64_t I = 0; I < nc; ++I) {
+    cols.clear();
+    acc.clear();
+    for (int32_t mi = start[I]; mi < start[I + 1]; ++mi) {
+      int64_t u = members[mi];
+      for (int32_t e = F.rowptr[u]; e < F.rowptr[u + 1]; ++e) {
+        int32_t J = agg[F.col[e]];
+        if (J == I) continue;
+        if (mark[J] < 0) {
+          mark[J] = (int32_t)cols.size();
+          cols.push_back(J);
+          acc.push_back(0.0);
+        }
+        acc[mark[J]] += F.w[e];
+      }
+    }
+    std::vector<int32_t> idx(cols.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cols[a] < cols[b]; });
+    double d = 0;
+    for (int i : idx) {
+      C.col.push_back(cols[i]);
+      C.w.push_back(acc[i]);
+      d += acc[i];
+    }
+    C.deg.push_back(d);
+    for (int32_t J : cols) mark[J] = -1;
+    C.rowptr[I + 1] = (int32_t)C.col.size();
+  }
+  return C;
+}
+
+// Dense pseudoinverse of a connected graph Laplacian via the grounded inverse.
+std::vector<double> laplacian_pinv(const BLevel& L) {
+  const int64_t n = L.n;
+  std::vector<double> out(n * n, 0.0);
+  if (n <= 1) return out;
+  const int64_t m = n - 1;  // ground node 0
+  std::vector<double> A(m * m, 0.0);
+  for (int64_t u = 1; u < n; ++u) {
+    A[(u - 1) * m + (u - 1)] = L.deg[u];
+    for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e) {
+      int64_t v = L.col[e];
+      if (v >= 1) A[(u - 1) * m + (v - 1)] -= L.w[e];
+    }
+  }
+  // Cholesky A = C C^T (lower), in place
+  for (int64_t j = 0; j < m; ++j) {
+    double s = A[j * m + j];
+    for (int64_t k = 0; k < j; ++k) s -= A[j * m + k] * A[j * m + k];
+    if (!(s > 0)) fail(CFC_E_INTERNAL, "coarsest grounded Laplacian is not positive definite");
+    const double cjj = std::sqrt(s);
+    A[j * m + j] = cjj;
+    for (int64_t i = j + 1; i < m; ++i) {
+      double t = A[i * m + j];
+      for (int64_t k = 0; k < j; ++k) t -= A[i * m + k] * A[j * m + k];
+      A[i * m + j] = t / cjj;
+    }
+  }
+  // G = A^-1 = C^-T C^-1: invert C (lower) then form Cinv^T Cinv
+  std::vector<double> Ci(m * m, 0.0);
+  for (int64_t j = 0; j < m; ++j) {
+    Ci[j * m + j] = 1.0 / A[j * m + j];
+    for (int64_t i = j + 1; i < m; ++i) {
+      double t = 0;
+      for (int64_t k = j; k < i; ++k) t -= A[i * m + k] * Ci[k * m + j];
+      Ci[i * m + j] = t / A[i * m + i];
+    }
+  }
+  std::vector<double> G(n * n, 0.0);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      double t = 0;
+      for (int64_t k = i; k < m; ++k) t += Ci[k * m + i] * Ci[k * m + j];
+      G[(i + 1) * n + (j + 1)] = t;
+      G[(j + 1) * n + (i + 1)] = t;
+    }
+  // L^+ = Pi G Pi
+  std::vector<double> rs(n, 0.0);
+  double tot = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0;
+    for (int64_t j = 0; j < n; ++j) s += G[i * n + j];
+    rs[i] = s;
+    tot += s;
+  }
+  const double inv = 1.0 / double(n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j)
+      out[i * n + j] = G[i * n + j] - rs[i] * inv - rs[j] * inv + tot * inv * inv;
+  return out;
+}
+
+}  // namespace
+
+void build_hierarchy(Graph& g, const cfc_setup_params& p) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (p.coarsest_max < 1 || p.coarsest_max > 4096) fail(CFC_E_INVALID, "coarsest_max must be in [1, 4096]");
+  if (p.agg_cap < 2 || p.agg_cap > 64) fail(CFC_E_INVALID, "agg_cap must be in [2, 64]");
+  if (p.test_vectors < 1 || p.test_vectors > 64) fail(CFC_E_INVALID, "test_vectors must be in [1, 64]");
+  if (p.relax_sweeps < 0 || p.relax_sweeps > 100) fail(CFC_E_INVALID, "relax_sweeps must be in [0, 100]");
+  if (!(p.omega > 0 && p.omega < 1)) fail(CFC_E_INVALID, "omega must be in (0, 1)");
+  if (!(p.mu > 0 && p.mu < 2)) fail(CFC_E_INVALID, "mu must be in (0, 2)");
+  std::vector<BLevel> B(1);
+  B[0].n = g.n;
+  B[0].rowptr = g.rowptr;
+  B[0].col = g.col;
+  B[0].w = g.w;
+  B[0].deg = g.deg;
+  while (B.back().n > p.coarsest_max && (int)B.size() < CFC_MAX_LEVELS) {
+    BLevel& F = B.back();
+    std::vector<int32_t> agg;
+    int64_t nc = aggregate(F, (int)B.size() - 1, p, agg);
+    if (nc >= F.n) break;  // no progress (cannot happen on a connected graph with n >= 2)
+    BLevel C = galerkin(F, agg, nc);
+    F.agg = std::move(agg);
+    F.nagg = nc;
+    B.push_back(std::move(C));
+  }
+  if (B.back().n > 4096) fail(CFC_E_INTERNAL, "coarsening stalled above 4096 nodes");
+  const int L = (int)B.size();
+  // nested renumbering, coarsest first
+  std::vector<std::vector<int32_t>> order(L), newid(L);
+  order[L - 1].resize(B[L - 1].n);
+  std::iota(order[L - 1].begin(), order[L - 1].end(), 0);
+  for (int l = L - 2; l >= 0; --l) {
+    const BLevel& F = B[l];
+    std::vector<int32_t> start(F.nagg + 1, 0), mem(F.n);
+    for (int64_t u = 0; u < F.n; ++u) start[F.agg[u] + 1]++;
+    for (int64_t i = 0; i < F.nagg; ++i) start[i + 1] += start[i];
+    std::vector<int32_t> pos(start.begin(), start.end() - 1);
+    for (int64_t u = 0; u < F.n; ++u) mem[pos[F.agg[u]]++] = (int32_t)u;
+    order[l].reserve(F.n);
+    for (int32_t I : order[l + 1])
+      for (int32_t k = start[I]; k < start[I + 1]; ++k) order[l].push_back(mem[k]);
+  }
+  for (int l = 0; l < L; ++l) {
+    newid[l].assign(B[l].n, -1);
+    for (int64_t i = 0; i < B[l].n; ++i) newid[l][order[l][i]] = (int32_t)i;
+  }
+  Hierarchy H;
+  H.omega = p.omega;
+  H.mu = p.mu;
+  H.lv.resize(L);
+  for (int l = 0; l < L; ++l) {
+    const BLevel& F = B[l];
+    HostLevel& O = H.lv[l];
+    O.n = F.n;
+    O.rowptr.assign(F.n + 1, 0);
+    O.col.reserve(F.col.size());
+    O.w.reserve(F.w.size());
+    O.deg.resize(F.n);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t r = 0; r < F.n; ++r) {
+      int32_t old = order[l][r];
+      row.clear();
+      for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e) row.emplace_back(newid[l][F.col[e]], F.w[e]);
+      std::sort(row.begin(), row.end());
+      for (auto& x : row) { O.col.push_back(x.first); O.w.push_back(x.second); }
+      O.rowptr[r + 1] = (int32_t)O.col.size();
+      O.deg[r] = F.deg[old];
+    }
+    if (l + 1 < L) {
+      O.agg.resize(F.n);
+      for (int64_t r = 0; r < F.n; ++r) O.agg[r] = newid[l + 1][F.agg[order[l][r]]];
+      O.aggptr.assign(F.nagg + 1, 0);
+      for (int64_t r = 0; r < F.n; ++r) O.aggptr[O.agg[r] + 1]++;
+      for (int64_t i = 0; i < F.nagg; ++i) O.aggptr[i + 1] += O.aggptr[i];
+      for (int64_t r = 1; r < F.n; ++r)
+        if (O.agg[r] < O.agg[r - 1]) fail(CFC_E_INTERNAL, "aggregates are not contiguous");
+    }
+  }
+  // coarsest pseudoinverse in final numbering
+  {
+    BLevel C;
+    C.n = H.lv[L - 1].n;
+    C.rowptr = H.lv[L - 1].rowptr;
+    C.col = H.lv[L - 1].col;
+    C.w = H.lv[L - 1].w;
+    C.deg = H.lv[L - 1].deg;
+    H.cpinv = laplacian_pinv(C);
+  }
+  H.perm = newid[0];
+  H.iperm = order[0];
+  H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  g.H = std::move(H);
+  g.have_h = true;
+}
+
+}  // namespace cfc

@@ -1,0 +1,98 @@
+// Host-visible interface of the device kernels (one table per block width W
+// and element type).  All arrays are node-major: an n x W block stores node
+// u's W values contiguously at offset u*W.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cfc {
+
+constexpr int kBlock = 256;      // threads per workgroup
+constexpr int kMaxGrid = 2048;   // workgroups of kernels that emit partial sums
+
+// One multigrid level as the kernels see it (element type T chosen by table).
+struct LevelArgs {
+  int n = 0;        // rows
+  int nagg = 0;     // aggregates (rows of the next level); 0 on the coarsest
+  const int* rowptr = nullptr;
+  const int* col = nullptr;
+  const void* w = nullptr;    // T[nnz] conductances, nullptr = all ones
+  const void* deg = nullptr;  // T[n] D_ii
+  const void* sd = nullptr;   // T[n] omega / D_ii (0 for an isolated node)
+  const int* agg = nullptr;   // [n] row -> next-level row
+  const int* aggptr = nullptr;// [nagg+1] aggregate row ranges
+  double omega = 2.0 / 3.0;
+  double mu = 1.5;
+};
+
+// Right-hand side of the FP64 residual kernel.
+struct RhsArgs {
+  int kind = 0;                  // 0 = dense FP64 n x W, 1 = pairs e_s - e_t
+  const double* dense = nullptr;
+  const int* ps = nullptr;       // [W] row of +1 (or -1 = none)
+  const int* pt = nullptr;       // [W] row of -1 (or -1 = none)
+};
+
+// Scalars kept per column on the device (double[kNScal][W]).
+enum Scal { S_RZ = 0, S_ALPHA, S_BETA, S_RR, S_CS, S_PQ, S_R64, S_N };
+
+struct KernTable {
+  int W = 0;
+  int esize = 0;  // sizeof(T)
+  int rg = 0;     // rows (row groups) per workgroup
+  // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q
+  void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, const double* scal,
+                  int first, double* part, hipStream_t);
+  // Level-0 update and pre-smooth/residual/restrict:
+  //   update: r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, partials |r_out|^2, sum x
+  //   restrict (if nagg > 0): bc[I] = sum_{u in I} (b - L S b)_u with b = r_out, S = omega D^-1
+  void (*update_restrict)(const LevelArgs&, const void* r_in, const void* q, const void* p,
+                          void* x, void* r_out, void* bc, const double* scal, int first,
+                          int do_update, double* part_rr, double* part_cs, hipStream_t);
+  // Coarse-level pre-smooth/residual/restrict from b (no update).
+  void (*restrict_)(const LevelArgs&, const void* b, void* bc, hipStream_t);
+  // Prolong + post-smooth: xt = S b + mu xc[agg], x = xt + S (b - L xt); partial b.x if part
+  void (*prolong_smooth)(const LevelArgs&, const void* b, const void* xc, void* x,
+                         double* part_rz, hipStream_t);
+  // Coarsest solve x = Lc^+ b (FP64 arithmetic); Lc^+ is nc_pad x nc_pad.
+  void (*coarse)(int nc, int nc_pad, const double* pinv, const void* b, void* x, hipStream_t);
+  // Partial dots b.x over n rows (for the single-level case).
+  void (*dot)(int n, const void* a, const void* b, double* part, hipStream_t);
+  // FP64 residual r = b - L x (x64 may be null = 0); r_out of element type T;
+  // partial |r|^2.
+  void (*residual64)(const LevelArgs& l64, const double* x64, RhsArgs rhs, void* r_out,
+                     double* part_rr, hipStream_t);
+  // x64 = (first ? 0 : x64) + d - cs/n  (d of element type T; cs from scal)
+  void (*xupdate64)(int n, double* x64, const void* d, const double* scal, int first, hipStream_t);
+  // Projection right-hand sides (Algorithm 1): Y[u, j] for systems i0 + j < k.
+  void (*jl_rhs)(const LevelArgs& l64, const int* iperm, uint64_t seed, int64_t i0, int64_t k,
+                 double* Y, hipStream_t);
+  // Per-row |x_u|^2 accumulated into N (double[n]) and partial column sums.
+  void (*jl_rownorm)(int n, const double* x64, int ncols, double* N, double* part_cs, hipStream_t);
+  // T[u] += x_u . s  (s = column sums, scal S_CS)
+  void (*jl_rowdot)(int n, const double* x64, int ncols, const double* scal, double* T, hipStream_t);
+  void (*zero)(void* p, size_t bytes, hipStream_t);
+};
+
+// Tables for element type float (FP32 inner solver) and double.
+const KernTable* kern_table(int W, bool fp64);
+int grid_for(int units, int rows_per_block);
+
+// Sum partials[g][W] over g (fixed order) into scal rows; op selects the
+// scalar update (see Finalize in kern_impl.hpp).
+enum FinOp { F_ALPHA = 0, F_RZINIT = 1, F_BETA = 2, F_R64 = 3, F_CS = 4 };
+void finalize(int W, int op, int g0, const double* p0, int g1, const double* p1, int g2,
+              const double* p2, double* scal, hipStream_t s);
+// out[j] = x64[s_j, j] - x64[t_j, j] for j < ncols
+void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt, double* out,
+               hipStream_t s);
+// out[i] = src[idx[i]] for i < q
+void gather(int q, const double* src, const int* idx, double* out, hipStream_t s);
+// x64[u, j] = 0 for every row u and every column j with flag[j] != 0
+void zero_cols(int n, int W, double* x64, const int* flag, hipStream_t s);
+// fill with zero bytes by a kernel (graph-capture friendly)
+void zero_fill(void* p, size_t bytes, hipStream_t s);
+// sum of x[0..n) into *out (two kernels, fixed order)
+void reduce_sum(int n, const double* x, double* part, double* out, hipStream_t s);
+
+}  // namespace cfc

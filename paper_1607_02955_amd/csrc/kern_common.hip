@@ -1,0 +1,191 @@
+// Width-independent kernels (finalize of partial sums, gathers) and the
+// per-width table dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kern.hpp"
+
+namespace cfc {
+
+const KernTable* kern_table_1(bool);
+const KernTable* kern_table_32(bool);
+const KernTable* kern_table_64(bool);
+const KernTable* kern_table_128(bool);
+const KernTable* kern_table_256(bool);
+const KernTable* kern_table_512(bool);
+
+const KernTable* kern_table(int W, bool fp64) {
+  switch (W) {
+    case 1: return kern_table_1(fp64);
+    case 32: return kern_table_32(fp64);
+    case 64: return kern_table_64(fp64);
+    case 128: return kern_table_128(fp64);
+    case 256: return kern_table_256(fp64);
+    case 512: return kern_table_512(fp64);
+    default: return nullptr;
+  }
+}
+
+int grid_for(int units, int rg) {
+  if (units <= 0) return 0;
+  int tiles = (units + rg - 1) / rg;
+  int g = std::min(tiles, kMaxGrid);
+  if (g >= 64) g &= ~7;
+  return g;
+}
+
+namespace {
+
+// Sum partial rows g = 0..G-1 of up to three arrays, per column, in a fixed
+// order, then apply the scalar update of the PCG / refinement step.
+__global__ __launch_bounds__(256) void k_finalize(int W, int op, int g0, const double* __restrict__ p0,
+                                                  int g1, const double* __restrict__ p1, int g2,
+                                                  const double* __restrict__ p2,
+                                                  double* __restrict__ scal) {
+  const int CH = W < 64 ? W : 64;
+  const int S = 256 / CH;
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x * CH + tid % CH;
+  const int sp = tid / CH;
+  __shared__ double red[3][256];
+  double s0 = 0, s1 = 0, s2 = 0;
+  if (sp < S && c < W) {
+    for (int g = sp; g < g0; g += S) s0 += p0[(size_t)g * W + c];
+    if (p1)
+      for (int g = sp; g < g1; g += S) s1 += p1[(size_t)g * W + c];
+    if (p2)
+      for (int g = sp; g < g2; g += S) s2 += p2[(size_t)g * W + c];
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  red[2][tid] = s2;
+  __syncthreads();
+  if (sp != 0 || c >= W) return;
+  double t0 = 0, t1 = 0, t2 = 0;
+  for (int s = 0; s < S; ++s) {
+    t0 += red[0][s * CH + tid];
+    t1 += red[1][s * CH + tid];
+    t2 += red[2][s * CH + tid];
+  }
+  switch (op) {
+    case F_ALPHA: {
+      const double rz = scal[S_RZ * W + c];
+      scal[S_PQ * W + c] = t0;
+      scal[S_ALPHA * W + c] = (t0 > 0 && rz > 0 && isfinite(rz / t0)) ? rz / t0 : 0.0;
+      break;
+    }
+    case F_RZINIT:
+      scal[S_RZ * W + c] = t0;
+      scal[S_BETA * W + c] = 0.0;
+      break;
+    case F_BETA: {
+      const double rz = scal[S_RZ * W + c];
+      const double beta = (rz > 0 && t0 > 0) ? t0 / rz : 0.0;
+      scal[S_BETA * W + c] = isfinite(beta) ? beta : 0.0;
+      scal[S_RZ * W + c] = t0;
+      scal[S_RR * W + c] = t1;
+      scal[S_CS * W + c] = t2;
+      break;
+    }
+    case F_R64:
+      scal[S_R64 * W + c] = t0;
+      break;
+    case F_CS:
+      scal[S_CS * W + c] = t0;
+      break;
+  }
+}
+
+__global__ void k_pair_diff(int W, int ncols, const double* __restrict__ x,
+                            const int* __restrict__ ps, const int* __restrict__ pt,
+                            double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  const int s = ps[j], t = pt[j];
+  out[j] = (s >= 0 && t >= 0) ? x[(size_t)s * W + j] - x[(size_t)t * W + j] : 0.0;
+}
+
+__global__ void k_gather(int q, const double* __restrict__ src, const int* __restrict__ idx,
+                         double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < q) out[i] = src[idx[i]];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_part(int n, const double* __restrict__ x,
+                                                     double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_reduce_final(int g, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0;
+    for (int i = 0; i < g; ++i) s += part[i];
+    *out = s;
+  }
+}
+
+__global__ void k_zero(uint32_t* p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_zero_cols(int n, int W, double* __restrict__ x, const int* __restrict__ flag) {
+  const size_t total = (size_t)n * W;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x)
+    if (flag[i % W]) x[i] = 0.0;
+}
+
+}  // namespace
+
+void zero_cols(int n, int W, double* x64, const int* flag, hipStream_t s) {
+  const size_t total = (size_t)n * W;
+  if (!total) return;
+  const int g = (int)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero_cols, dim3(g), dim3(256), 0, s, n, W, x64, flag);
+}
+
+void zero_fill(void* p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  if (!words || !p) return;
+  const int g = (int)std::min<size_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, s, (uint32_t*)p, words);
+}
+
+void finalize(int W, int op, int g0, const double* p0, int g1, const double* p1, int g2,
+              const double* p2, double* scal, hipStream_t s) {
+  const int CH = W < 64 ? W : 64;
+  hipLaunchKernelGGL(k_finalize, dim3((W + CH - 1) / CH), dim3(256), 0, s, W, op, g0, p0, g1, p1,
+                     g2, p2, scal);
+}
+
+void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt, double* out,
+               hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_pair_diff, dim3((ncols + 255) / 256), dim3(256), 0, s, W, ncols, x64, ps, pt,
+                     out);
+}
+
+void gather(int q, const double* src, const int* idx, double* out, hipStream_t s) {
+  if (q <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3((q + 255) / 256), dim3(256), 0, s, q, src, idx, out);
+}
+
+void reduce_sum(int n, const double* x, double* part, double* out, hipStream_t s) {
+  const int g = std::max(1, std::min((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_reduce_part, dim3(g), dim3(256), 0, s, n, x, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, g, part, out);
+}
+
+}  // namespace cfc

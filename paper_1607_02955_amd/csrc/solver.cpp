@@ -1,0 +1,414 @@
+// Solve driver: device copy of the hierarchy, per-block workspaces, the
+// preconditioned CG inner solver, FP64 iterative refinement, and the
+// estimator reductions.
+//
+// One block of W right-hand sides is solved at a time (Eq. 1, L x = b):
+//   outer (FP64):  r = b - L x, per-column ||r|| / ||b|| <= tol (Sec. 3.1),
+//                  else solve L d ~= r and x += d - mean(d) (the
+//                  mean-zero representative, Sec. 2: x is fixed only up to
+//                  an additive constant);
+//   inner (T = float in mixed mode, double in FP64 mode): CG preconditioned
+//                  by one symmetric V-cycle of the aggregation hierarchy.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+
+#include "kern.hpp"
+#include "solver.hpp"
+
+namespace cfc {
+
+// ---------------------------------------------------------------------------
+// device upload
+
+namespace {
+template <class T>
+void upload(Ctx* c, DBuf& d, const std::vector<T>& h, hipStream_t s) {
+  d.alloc(c, h.size() * sizeof(T));
+  if (!h.empty()) CFC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+}  // namespace
+
+void upload_hierarchy(Graph& g) {
+  Ctx* c = g.ctx;
+  if (c->host_only()) return;
+  CFC_HIP(hipSetDevice(c->device));
+  auto D = std::make_unique<DevHierarchy>();
+  const Hierarchy& H = g.H;
+  const int L = (int)H.lv.size();
+  D->lv.resize(L);
+  hipStream_t s = c->stream;
+  for (int l = 0; l < L; ++l) {
+    const HostLevel& h = H.lv[l];
+    DevLevel& d = D->lv[l];
+    d.n = (int)h.n;
+    d.nnz = (int)h.nnz();
+    d.nagg = h.aggptr.empty() ? 0 : (int)h.aggptr.size() - 1;
+    d.unit = (l == 0) && g.unit;
+    upload(c, d.rowptr, h.rowptr, s);
+    upload(c, d.col, h.col, s);
+    std::vector<float> w32(h.w.size()), deg32(h.n), sd32(h.n);
+    std::vector<double> sd64(h.n);
+    for (size_t i = 0; i < h.w.size(); ++i) w32[i] = (float)h.w[i];
+    for (int64_t r = 0; r < h.n; ++r) {
+      // FP32 diagonal = FP32 sum of the FP32 off-diagonals, so that the FP32
+      // operator keeps its row sums (L 1 = 0) as closely as FP32 allows.
+      float sacc = 0.f;
+      for (int32_t e = h.rowptr[r]; e < h.rowptr[r + 1]; ++e) sacc += w32[e];
+      deg32[r] = sacc;
+      sd32[r] = sacc > 0 ? (float)(H.omega / (double)sacc) : 0.f;
+      sd64[r] = h.deg[r] > 0 ? H.omega / h.deg[r] : 0.0;
+    }
+    if (!d.unit) {
+      upload(c, d.w32, w32, s);
+      upload(c, d.w64, h.w, s);
+    }
+    upload(c, d.deg32, deg32, s);
+    upload(c, d.deg64, h.deg, s);
+    upload(c, d.sdinv32, sd32, s);
+    upload(c, d.sdinv64, sd64, s);
+    if (!h.agg.empty()) {
+      upload(c, d.agg, h.agg, s);
+      upload(c, d.aggptr, h.aggptr, s);
+    }
+    d.omega64 = H.omega;
+    D->bytes += d.rowptr.bytes + d.col.bytes + d.w32.bytes + d.w64.bytes + d.deg32.bytes +
+                d.deg64.bytes + d.sdinv32.bytes + d.sdinv64.bytes + d.agg.bytes + d.aggptr.bytes;
+  }
+  // coarsest pseudoinverse, zero-padded to a multiple of 16
+  const int nc = (int)H.lv[L - 1].n;
+  const int ncp = (nc + 15) / 16 * 16;
+  std::vector<double> P((size_t)ncp * ncp, 0.0);
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) P[(size_t)i * ncp + j] = H.cpinv[(size_t)i * nc + j];
+  upload(c, D->cpinv, P, s);
+  D->nc = nc;
+  upload(c, D->iperm, H.iperm, s);
+  D->bytes += D->cpinv.bytes + D->iperm.bytes;
+  CFC_HIP(hipStreamSynchronize(s));
+  g.ws.clear();
+  g.D = std::move(D);
+  g.jl = JLSketch();
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+
+static LevelArgs level_args(const Graph& g, int l, bool fp64) {
+  const DevLevel& d = g.D->lv[l];
+  LevelArgs a;
+  a.n = d.n;
+  a.nagg = d.nagg;
+  a.rowptr = d.rowptr.as<int>();
+  a.col = d.col.as<int>();
+  a.w = fp64 ? (const void*)d.w64.p : (const void*)d.w32.p;
+  if (d.unit) a.w = nullptr;
+  a.deg = fp64 ? d.deg64.p : d.deg32.p;
+  a.sd = fp64 ? d.sdinv64.p : d.sdinv32.p;
+  a.agg = d.agg.as<int>();
+  a.aggptr = d.aggptr.as<int>();
+  a.omega = g.H.omega;
+  a.mu = g.H.mu;
+  return a;
+}
+
+Workspace::~Workspace() {
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s) {
+  for (auto& w : g.ws)
+    if (w->W == W && w->fp64 == fp64) return *w;
+  Ctx* c = g.ctx;
+  auto ws = std::make_unique<Workspace>();
+  Workspace& w = *ws;
+  w.W = W;
+  w.fp64 = fp64;
+  w.kt = kern_table(W, fp64);
+  if (!w.kt) fail(CFC_E_INVALID, "unsupported block width " + std::to_string(W));
+  const int L = (int)g.D->lv.size();
+  w.nlev = L;
+  w.la.resize(L);
+  for (int l = 0; l < L; ++l) w.la[l] = level_args(g, l, fp64);
+  w.la64 = level_args(g, 0, true);
+  const size_t es = fp64 ? 8 : 4;
+  const size_t n0 = (size_t)g.D->lv[0].n;
+  const size_t blk = n0 * W * es;
+  for (DBuf* b : {&w.x, &w.ra, &w.rb, &w.p, &w.q, &w.z}) b->alloc(c, blk);
+  w.b.resize(L);
+  w.xl.resize(L);
+  for (int l = 1; l < L; ++l) {
+    w.b[l].alloc(c, (size_t)g.D->lv[l].n * W * es);
+    w.xl[l].alloc(c, (size_t)g.D->lv[l].n * W * es);
+  }
+  w.x64.alloc(c, n0 * W * 8);
+  w.pairs.alloc(c, 2 * W * sizeof(int) + 2 * (W + 1) * sizeof(int));
+  w.part.alloc(c, (size_t)P_COUNT * kMaxGrid * W * sizeof(double));
+  w.scal.alloc(c, (size_t)S_N * W * sizeof(double));
+  w.dvec.alloc(c, (size_t)(W + 1024) * sizeof(double));
+  CFC_HIP(hipHostMalloc(&w.pinned, (size_t)(4 * W + 64) * sizeof(double), hipHostMallocDefault));
+  w.kt->zero(w.scal.p, w.scal.bytes, s);
+  w.kt->zero(w.part.p, w.part.bytes, s);
+  g.ws.push_back(std::move(ws));
+  return *g.ws.back();
+}
+
+double* Workspace::part_ptr(int which) const {
+  return part.as<double>() + (size_t)which * kMaxGrid * W;
+}
+
+// ---------------------------------------------------------------------------
+// model of algorithmic bytes (compulsory traffic per launch; gathered rows
+// counted once) used by the roofline report
+
+static double mat_bytes(const DevLevel& d, bool weighted, size_t es) {
+  return 4.0 * (d.n + 1) + 4.0 * d.nnz + (weighted ? es * (double)d.nnz : 0.0) + 2.0 * es * d.n;
+}
+
+// ---------------------------------------------------------------------------
+// one V-cycle (and, when update is set, the PCG update of level 0 fused into
+// its first kernel): z = V(r)
+
+void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
+  Workspace& w = *ws;
+  const KernTable& k = *w.kt;
+  hipStream_t s = stream;
+  const int L = w.nlev;
+  const size_t es = w.fp64 ? 8 : 4;
+  const double nw = (double)w.W * es;
+  const DevLevel& d0 = g->D->lv[0];
+  const void* rsrc = update ? r_out : r_in;
+  if (L == 1) {
+    if (update) {
+      LevelArgs a = w.la[0];
+      a.nagg = 0;
+      k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
+                        1, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
+      g_rr = g_cs = grid_for(d0.n, k.rg);
+      bytes += d0.n * nw * (first_x ? 4 : 6);
+    }
+    k.coarse(g->D->nc, (g->D->nc + 15) / 16 * 16, g->D->cpinv.as<double>(), rsrc, w.z.p, s);
+    k.dot(d0.n, rsrc, w.z.p, w.part_ptr(P_RZ), s);
+    g_rz = grid_for(d0.n, k.rg);
+    bytes += d0.n * nw * 3 + 8.0 * d0.n * d0.n;
+    return;
+  }
+  k.update_restrict(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.b[1].p, w.scal.as<double>(),
+                    first_x, update ? 1 : 0, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
+  if (update) g_rr = g_cs = grid_for(d0.nagg, k.rg);
+  bytes += d0.n * nw * (update ? (first_x ? 4 : 6) : 1) + d0.nagg * nw +
+           mat_bytes(d0, !d0.unit, es) + 4.0 * (d0.nagg + 1);
+  for (int l = 1; l + 1 < L; ++l) {
+    const DevLevel& d = g->D->lv[l];
+    k.restrict_(w.la[l], w.b[l].p, w.b[l + 1].p, s);
+    bytes += d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * (d.nagg + 1);
+  }
+  const int nc = g->D->nc;
+  k.coarse(nc, (nc + 15) / 16 * 16, g->D->cpinv.as<double>(), w.b[L - 1].p, w.xl[L - 1].p, s);
+  bytes += 2.0 * nc * nw + 8.0 * nc * nc;
+  for (int l = L - 2; l >= 1; --l) {
+    const DevLevel& d = g->D->lv[l];
+    k.prolong_smooth(w.la[l], w.b[l].p, w.xl[l + 1].p, w.xl[l].p, nullptr, s);
+    bytes += 2.0 * d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * d.n;
+  }
+  prof_begin(K_PROLONG0);
+  k.prolong_smooth(w.la[0], rsrc, w.xl[1].p, w.z.p, w.part_ptr(P_RZ), s);
+  const double pb = 2.0 * d0.n * nw + d0.nagg * nw + mat_bytes(d0, !d0.unit, es) + 4.0 * d0.n;
+  prof_end(K_PROLONG0, pb);
+  g_rz = grid_for(d0.n, k.rg);
+  bytes += pb;
+}
+
+void Solver::prof_begin(int which) {
+  if (!profile || which != prof_kernel) return;
+  hipEvent_t a;
+  CFC_HIP(hipEventCreate(&a));
+  CFC_HIP(hipEventRecord(a, stream));
+  prof_ev.push_back(a);
+}
+void Solver::prof_end(int which, double b) {
+  if (!profile || which != prof_kernel) return;
+  hipEvent_t e;
+  CFC_HIP(hipEventCreate(&e));
+  CFC_HIP(hipEventRecord(e, stream));
+  prof_ev.push_back(e);
+  prof_bytes += b;
+  prof_launches++;
+}
+void Solver::prof_collect() {
+  for (size_t i = 0; i + 1 < prof_ev.size(); i += 2) {
+    float ms = 0;
+    CFC_HIP(hipEventSynchronize(prof_ev[i + 1]));
+    CFC_HIP(hipEventElapsedTime(&ms, prof_ev[i], prof_ev[i + 1]));
+    prof_ms += ms;
+  }
+  for (auto e : prof_ev) (void)hipEventDestroy(e);
+  prof_ev.clear();
+}
+
+// Read the per-column squared residuals S_RR to the host (synchronises).
+void Solver::read_scal(int which, double* out) {
+  Workspace& w = *ws;
+  CFC_HIP(hipMemcpyAsync(w.pinned, w.scal.as<double>() + (size_t)which * w.W, w.W * sizeof(double),
+                         hipMemcpyDeviceToHost, stream));
+  CFC_HIP(hipStreamSynchronize(stream));
+  std::memcpy(out, w.pinned, w.W * sizeof(double));
+}
+
+// Preconditioned CG on L d = r0 (r0 in ws.ra); result d in ws.x.  Returns
+// the iteration count.
+int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every) {
+  Workspace& w = *ws;
+  const KernTable& k = *w.kt;
+  hipStream_t s = stream;
+  const DevLevel& d0 = g->D->lv[0];
+  const size_t es = w.fp64 ? 8 : 4;
+  const double nw = (double)w.W * es;
+  const int W = w.W;
+  vcycle(false, false, w.ra.p, nullptr);
+  finalize(W, F_RZINIT, g_rz, w.part_ptr(P_RZ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s);
+  std::vector<double> rr(W);
+  const double tol2 = inner_tol * inner_tol;
+  int it = 0;
+  void* ra = w.ra.p;
+  void* rb = w.rb.p;
+  while (it < max_inner) {
+    ++it;
+    const bool first = it == 1;
+    prof_begin(K_SPMM);
+    k.spmm_pq(w.la[0], w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first, w.part_ptr(P_PQ), s);
+    const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es);
+    prof_end(K_SPMM, sb);
+    bytes += sb;
+    finalize(W, F_ALPHA, grid_for(d0.n, k.rg), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
+             w.scal.as<double>(), s);
+    vcycle(true, first, ra, rb);
+    finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
+             w.scal.as<double>(), s);
+    std::swap(ra, rb);
+    if (it % check_every == 0 || it == max_inner) {
+      read_scal(S_RR, rr.data());
+      bool done = true;
+      for (int j = 0; j < W; ++j) {
+        if (!(rr0[j] > 0)) continue;
+        if (!std::isfinite(rr[j])) continue;  // reported by the outer residual
+        if (rr[j] > tol2 * rr0[j]) { done = false; break; }
+      }
+      if (done) break;
+    }
+  }
+  // keep the latest residual in ws.ra for callers that look at it
+  if (ra != w.ra.p) std::swap(w.ra.p, w.rb.p);
+  return it;
+}
+
+// Solve one block.  rhs describes b (pairs or dense FP64 in ws.rhs, internal
+// numbering); ncols columns are live.  On return ws.x64 holds x (mean-zero).
+void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& p, int32_t* status,
+                         double* final_rel) {
+  Workspace& w = *ws;
+  const KernTable& k = *w.kt;
+  hipStream_t s = stream;
+  const int W = w.W;
+  const DevLevel& d0 = g->D->lv[0];
+  const size_t es = w.fp64 ? 8 : 4;
+  std::vector<double> r64(W), b2(W), rel(W, 0.0);
+  bool have_x = false;
+  const int gres = grid_for(d0.n, k.rg);
+  double cur_max = 1.0;
+  int step = 0;
+  for (;; ++step) {
+    k.residual64(w.la64, have_x ? w.x64.as<double>() : nullptr, rhs, w.ra.p, w.part_ptr(P_PQ), s);
+    bytes += d0.n * (double)W * ((have_x ? 8.0 : 0.0) + (rhs.kind == 0 ? 8.0 : 0.0) + es) +
+             (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
+    finalize(W, F_R64, gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s);
+    read_scal(S_R64, r64.data());
+    if (step == 0) b2 = r64;
+    bool all = true;
+    cur_max = 0;
+    for (int j = 0; j < W; ++j) {
+      if (j >= ncols || !(b2[j] > 0)) { rel[j] = 0; continue; }
+      rel[j] = std::sqrt(r64[j] / b2[j]);
+      if (!std::isfinite(rel[j])) continue;
+      cur_max = std::max(cur_max, rel[j]);
+      if (rel[j] > p.tol) all = false;
+    }
+    if (debug) {
+      std::fprintf(stderr, "[cfc] W=%d prec=%d step %d max_rel %.3e (col0 %.3e)\n", W, p.precision, step,
+                   cur_max, rel[0]);
+    }
+    if (all || step >= p.max_refine) break;
+    double itol = p.precision == CFC_PREC_FP64 ? std::max(0.5 * p.tol / cur_max, 1e-15)
+                                                : std::max(p.inner_tol, 0.5 * p.tol / cur_max);
+    itol = std::min(itol, 0.5);
+    const int its = pcg(r64, itol, p.max_inner, std::max(1, p.check_every));
+    if (debug) std::fprintf(stderr, "[cfc]   pcg its %d (inner tol %.2e)\n", its, itol);
+    inner_iters += its;
+    k.xupdate64(d0.n, w.x64.as<double>(), w.x.p, w.scal.as<double>(), have_x ? 0 : 1, s);
+    bytes += d0.n * (double)W * ((have_x ? 16.0 : 8.0) + es);
+    have_x = true;
+    refine_steps++;
+  }
+  if (!have_x) k.zero(w.x64.p, (size_t)d0.n * W * 8, s);
+  for (int j = 0; j < ncols; ++j) {
+    int32_t st = CFC_COL_OK;
+    if (!(b2[j] > 0)) st = (b2[j] == 0) ? CFC_COL_SKIPPED : CFC_COL_DIVERGED;
+    else if (!std::isfinite(rel[j])) st = CFC_COL_DIVERGED;
+    else if (rel[j] > p.tol) st = CFC_COL_NOT_CONVERGED;
+    if (status) status[j] = st;
+    if (final_rel) final_rel[j] = rel[j];
+    if (st == CFC_COL_OK || st == CFC_COL_SKIPPED) converged++;
+    if (std::isfinite(rel[j])) max_rel = std::max(max_rel, rel[j]);
+    else max_rel = INFINITY;
+  }
+  columns += ncols;
+  blocks++;
+}
+
+Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so) : g(&gr), params(p) {
+  if (!g->D) fail(CFC_E_STATE, "hierarchy not built on a device (call cfc_hierarchy_build)");
+  stream = so ? so : g->ctx->stream;
+  const char* dbg = std::getenv("CFC_DEBUG");
+  debug = dbg && dbg[0] == '1';
+  const char* pe = std::getenv("CFC_PROFILE");
+  profile = pe && pe[0] == '1';
+  const char* pk = std::getenv("CFC_PROFILE_KERNEL");
+  prof_kernel = (pk && std::strcmp(pk, "prolong") == 0) ? K_PROLONG0 : K_SPMM;
+  ws = &get_workspace(*g, p.block, p.precision == CFC_PREC_FP64, stream);
+  CFC_HIP(hipEventCreate(&ev0));
+  CFC_HIP(hipEventCreate(&ev1));
+  CFC_HIP(hipEventRecord(ev0, stream));
+}
+
+Solver::~Solver() {
+  for (auto e : prof_ev) (void)hipEventDestroy(e);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+void Solver::finish(cfc_solve_stats* st) {
+  CFC_HIP(hipEventRecord(ev1, stream));
+  CFC_HIP(hipEventSynchronize(ev1));
+  float ms = 0;
+  CFC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  prof_collect();
+  if (!st) return;
+  st->columns += columns;
+  st->converged += converged;
+  st->inner_iters += inner_iters;
+  st->refine_steps += refine_steps;
+  st->blocks += blocks;
+  st->block_width = ws->W;
+  st->precision = params.precision;
+  st->max_rel_residual = std::max(st->max_rel_residual, max_rel);
+  st->solve_ms += ms;
+  st->model_bytes += bytes;
+  st->spmm_ms += prof_ms;
+  st->spmm_bytes += prof_bytes;
+  st->spmm_launches += prof_launches;
+}
+
+}  // namespace cfc

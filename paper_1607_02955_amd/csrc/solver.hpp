@@ -1,0 +1,80 @@
+// Solver driver declarations.
+#pragma once
+#include <vector>
+
+#include "internal.hpp"
+#include "kern.hpp"
+
+namespace cfc {
+
+enum PartSlot { P_PQ = 0, P_RZ, P_RR, P_CS, P_COUNT };
+enum ProfKernel { K_SPMM = 0, K_PROLONG0 = 1 };
+
+// Device buffers for solving one block of W columns in one precision.
+struct Workspace {
+  int W = 0;
+  bool fp64 = false;
+  int nlev = 0;
+  const KernTable* kt = nullptr;
+  std::vector<LevelArgs> la;  // per level, element type of the inner solver
+  LevelArgs la64;             // level 0 in FP64
+  DBuf x, ra, rb, p, q, z;    // level 0, inner element type
+  std::vector<DBuf> b, xl;    // levels >= 1: right-hand side and iterate
+  DBuf x64;                   // FP64 solution block
+  DBuf rhs;                   // FP64 dense right-hand sides (on demand)
+  DBuf pairs;                 // int32 ps[W], pt[W], segment bounds
+  DBuf part;                  // FP64 partial sums [P_COUNT][kMaxGrid][W]
+  DBuf scal;                  // FP64 per-column scalars [S_N][W]
+  DBuf dvec;                  // FP64 scratch for per-column outputs
+  double* pinned = nullptr;   // pinned host staging
+  ~Workspace();
+  double* part_ptr(int which) const;
+};
+
+Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s);
+
+struct Solver {
+  Graph* g;
+  cfc_solve_params params;
+  Workspace* ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int g_rz = 0, g_rr = 0, g_cs = 0;
+  // statistics
+  int64_t columns = 0, converged = 0, inner_iters = 0, refine_steps = 0, blocks = 0;
+  double max_rel = 0, bytes = 0;
+  // kernel timing with HIP events on the launch stream (CFC_PROFILE=1)
+  bool profile = false;
+  bool debug = false;
+  int prof_kernel = K_SPMM;
+  std::vector<hipEvent_t> prof_ev;
+  double prof_ms = 0, prof_bytes = 0;
+  int64_t prof_launches = 0;
+
+  Solver(Graph& g, const cfc_solve_params& p, hipStream_t stream_override = nullptr);
+  ~Solver();
+  void vcycle(bool update, bool first_x, const void* r_in, void* r_out);
+  int pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
+  void solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& p, int32_t* status,
+                   double* final_rel);
+  void read_scal(int which, double* out);
+  void prof_begin(int which);
+  void prof_end(int which, double bytes);
+  void prof_collect();
+  void finish(cfc_solve_stats* st);
+};
+
+cfc_solve_params default_solve();
+// Pick W for the graph (autotuner; cached in the graph).
+int choose_block(Graph& g, const cfc_solve_params& p, int64_t ncols);
+
+// Estimators (estimators.cpp)
+void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_solve_params& p,
+                 cfc_solve_stats* st, int32_t* col_status);
+// Solve e_{s_j} - e_{t_j} (graph ids) and return x(s_j) - x(t_j) per column.
+void pair_solves(Graph& g, int64_t npairs, const int64_t* s, const int64_t* t, double* out,
+                 const cfc_solve_params& p, cfc_solve_stats* st, int32_t* col_status);
+void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p, cfc_solve_stats* st);
+void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* clo);
+
+}  // namespace cfc

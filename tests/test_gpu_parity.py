@@ -1,0 +1,179 @@
+"""GPU parity of the HIP solve path against the CPU oracle (through the C ABI).
+
+Tolerances: the solve is judged on relative farness / resistance error
+(<= 1e-6 at the tolerances used below, tighter in FP64 mode); estimator
+outputs must match the oracle's for the same seed to <= 1e-4 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimators as E
+from oracle import laplacian as LAP
+from oracle import resistance as R
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1607_02955_amd as cfc
+    return cfc.Context(0)
+
+
+def load(ctx, eg, **setup):
+    import paper_1607_02955_amd as cfc
+    g = cfc.Graph.from_edgelist(ctx, eg)
+    g.build_hierarchy(**setup)
+    return g
+
+
+def dense_R(eg):
+    Lp = R.pinv(LAP.of(eg, dense=True))
+    return Lp, R.resistance_matrix(Lp)
+
+
+def test_single_level_is_exact_pinv(ctx):
+    """n <= coarsest_max: the preconditioner is the MFMA pseudoinverse apply."""
+    eg = synth.random_connected(40, 100, seed=1)
+    say("single-level", eg.n, eg.m)
+    g = load(ctx, eg)
+    assert g.info()["levels"] == 1
+    _, Rm = dense_R(eg)
+    s = np.arange(40)
+    t = (s * 7 + 3) % 40
+    for W, prec in [(32, 1), (64, 0), (1, 1), (256, 0)]:
+        r = g.resistance(s, t, block=W, precision=prec, tol=1e-10)
+        np.testing.assert_allclose(r, Rm[s, t], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("W", [1, 32, 64, 128, 256, 512])
+def test_block_widths_weighted_random(ctx, W):
+    eg = synth.random_connected(1500, 6000, seed=W)
+    say("widths", W, eg.n, eg.m)
+    g = load(ctx, eg, coarsest_max=64)
+    assert g.info()["levels"] >= 3
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(W)
+    npairs = 3 * W + 7 if W > 1 else 9  # several blocks and a ragged tail
+    s = rng.integers(0, eg.n, npairs)
+    t = rng.integers(0, eg.n, npairs)
+    t[0] = s[0]  # e_v - e_v = 0
+    for prec, tol, rt in [(0, 1e-8, 1e-7), (1, 1e-10, 1e-9)]:
+        r, st = g.resistance(s, t, block=W, precision=prec, tol=tol, stats=True)
+        assert st["block_width"] == W and st["converged"] == npairs
+        np.testing.assert_allclose(r, Rm[s, t], rtol=rt, atol=1e-12)
+        assert r[0] == 0.0
+
+
+@pytest.mark.parametrize("maker,name", [
+    (lambda: synth.path_graph(300), "path"),
+    (lambda: synth.cycle_graph(301), "cycle"),
+    (lambda: synth.star_graph(3000), "star"),
+    (lambda: synth.complete_graph(80), "K80"),
+])
+def test_closed_forms(ctx, maker, name):
+    eg = maker()
+    say("closed form", name, eg.n, eg.m)
+    g = load(ctx, eg, coarsest_max=32)
+    n = eg.n
+    s = np.array([0, 1, n // 2, n - 1, 5])
+    t = np.array([n - 1, 2, 3, 0, 5])
+    r = g.resistance(s, t, tol=1e-9, block=64)
+    if name == "path":
+        want = np.abs(s - t).astype(float)
+    elif name == "cycle":
+        d = np.abs(s - t)
+        want = d * (n - d) / n
+    elif name == "star":
+        want = np.where(s == t, 0.0, np.where((s == 0) | (t == 0), 1.0, 2.0))
+    else:
+        want = np.where(s == t, 0.0, 2.0 / n)
+    np.testing.assert_allclose(r, want, rtol=1e-7, atol=1e-12)
+
+
+def test_exact_farness_grid32_fp64(ctx):
+    """Plain method on the 32 x 32 grid: 1023 solves to 1e-10 (FP64)."""
+    from tests.test_oracle_pins import grid_spectral_farness
+    eg = synth.grid(32)
+    g = load(ctx, eg)
+    want = grid_spectral_farness(32, 0, 0)
+    far, clo, st = g.farness_exact([0], precision=1, tol=1e-10, block=256, stats=True)
+    say("exact 32x32", far, st)
+    assert abs(far[0] / want - 1) < 1e-9
+    assert abs(clo[0] - 1023 / want) < 1e-9 * clo[0]
+    far2, _ = g.farness_exact([0, 528], tol=1e-10)  # mixed precision refined to 1e-10
+    Lp, _ = dense_R(eg)
+    np.testing.assert_allclose(far2, R.farness_dense(Lp, [0, 528]), rtol=1e-9)
+
+
+def test_solve_dense_matches_pinv(ctx):
+    import torch
+    eg = synth.barabasi_albert(4000, 4, seed=7)
+    g = load(ctx, eg)
+    Lp, _ = dense_R(eg)
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((70, eg.n))
+    B -= B.mean(axis=1, keepdims=True)
+    X, st, status = g.solve(B, stats=True, tol=1e-8)
+    say("dense solve", st)
+    want = (Lp @ B.T).T
+    assert np.all(status == 0)
+    np.testing.assert_allclose(X, want, atol=1e-7 * np.abs(want).max())
+    np.testing.assert_allclose(X.sum(axis=1), 0, atol=1e-9)
+    # device tensors in, device tensors out
+    Bt = torch.tensor(B[:5], device="cuda")
+    Xt = g.solve(Bt, tol=1e-8)
+    assert Xt.is_cuda
+    np.testing.assert_allclose(Xt.cpu().numpy(), want[:5], atol=1e-7 * np.abs(want).max())
+    # residual certificate with the oracle's operator
+    Ls = LAP.of(eg)
+    res = np.linalg.norm(B.T - Ls @ X.T, axis=0) / np.linalg.norm(B.T, axis=0)
+    assert res.max() <= 1e-8 * 1.01
+
+
+def test_sampling_matches_oracle_same_seed(ctx):
+    eg = synth.barabasi_albert(5000, 4, seed=11)
+    nodes = synth.query_nodes(eg.n, 6, seed=2)
+    g = load(ctx, eg)
+    far, clo, st = g.farness_sampling(nodes, k=60, seed=9, stats=True, tol=1e-8)
+    say("sampling", st)
+    of, oc, piv, d = E.sampling(LAP.of(eg), eg, nodes, 60, 9, tol=1e-12)
+    np.testing.assert_allclose(far, of, rtol=1e-6)
+    np.testing.assert_allclose(clo, oc, rtol=1e-6)
+
+
+def test_projection_matches_oracle_same_seed(ctx):
+    eg = synth.random_connected(2500, 9000, seed=13)
+    nodes = synth.query_nodes(eg.n, 10, seed=3)
+    g = load(ctx, eg)
+    st = g.jl_sketch(96, seed=5, stats=True, tol=1e-9, block=64)
+    say("jl", st)
+    far, clo = g.farness_jl(nodes)
+    of, oc, Z = E.projection(LAP.of(eg), eg, nodes, 96, 5, tol=1e-12)
+    np.testing.assert_allclose(far, of, rtol=1e-6)
+    np.testing.assert_allclose(clo, oc, rtol=1e-6)
+
+
+def test_edge_cases(ctx):
+    import paper_1607_02955_amd as cfc
+    g1 = cfc.Graph(ctx, 1, [], [])
+    g1.build_hierarchy()
+    assert g1.resistance([0], [0])[0] == 0.0
+    g2 = cfc.Graph(ctx, 2, [0], [1], [4.0]).build_hierarchy()
+    np.testing.assert_allclose(g2.resistance([0, 1], [1, 0], tol=1e-10), [0.25, 0.25], rtol=1e-10)
+    far, clo = g2.farness_exact([0], tol=1e-10)
+    np.testing.assert_allclose(far, [0.25], rtol=1e-10)
+    with pytest.raises(cfc.CfcError):
+        g2.resistance([0], [2])
+    with pytest.raises(cfc.CfcError):
+        g2.solve(np.array([1.0, 0.0]))  # does not sum to zero
+    with pytest.raises(cfc.CfcError, match="STATE"):
+        g2.farness_jl([0])
