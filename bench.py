@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the Laplacian-solve hot path on one MI355X.
+
+Workload (one "step"): the projection estimator of current-flow closeness
+(Sec. 5.2, Algorithm 1) on a Barabasi-Albert graph with n = 100,000 nodes and
+4 edges per new node (m = 399,990, unit weights): build the k = 512 right-hand
+sides (Q W^(1/2) B)_i, solve them as one 512-wide block with the FP32
+multigrid-preconditioned CG inside FP64 refinement to a per-column relative
+residual of 1e-6, reduce the solutions to per-node sketch norms, and answer
+the farness of 100 query nodes.  The metric is solved right-hand sides per
+second; inputs are resident in HBM when the timed region starts (the graph
+hierarchy is set up once, outside the timed region).
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(algorithmic bytes per launch over its HIP-event-timed duration on the launch
+stream), the CPU oracle timed on a bounded sample, and the plain FP64
+one-right-hand-side-at-a-time GPU solve for comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DOMINANT = os.environ.get("CFC_PROFILE_KERNEL", "prolong")
+KERNEL_NAMES = {"spmm": "k_spmm_pq", "prolong": "k_prolong_smooth", "restrict": "k_update_restrict"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kern_impl.hpp", "kern.hpp"):
+        with open(os.path.join(ROOT, "paper_1607_02955_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, kernel, launches_bytes):
+    """HBM traffic of the dominant kernel from the committed rocprofv3 PMC
+    summary, when it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAMES[kernel]}_{workload}.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_workload(name):
+    import synth
+    if name == "ba100k_jl512":
+        g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
+        return g, dict(kind="jl", k=512, block=512, tol=1e-6, queries=100)
+    if name == "grid32_exact":
+        g = synth.grid(32)
+        return g, dict(kind="exact", block=256, tol=1e-10, queries=1, precision=1)
+    if name == "rmat20_sampling":
+        g = synth.cached("rmat20", synth.rmat, 20, 16, seed=1)
+        return g, dict(kind="sampling", k=1000, block=256, tol=1e-6, queries=64)
+    if name == "road2048_jl256":
+        g = synth.cached("road2048", synth.road_grid, 2048, seed=1)
+        return g, dict(kind="jl", k=256, block=0, tol=1e-6, queries=32)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(eg, spec, budget_s=20.0):
+    """The oracle (plain FP64 Jacobi-preconditioned CG, numpy/scipy) on a
+    bounded sample of the same right-hand sides, single-threaded."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import estimators as E
+    from oracle import laplacian as LAP
+    from oracle import resistance as R
+
+    L = LAP.of(eg)
+    ctxm = threadpool_limits(1) if threadpool_limits else None
+    try:
+        if ctxm:
+            ctxm.__enter__()
+        if spec["kind"] == "jl":
+            Y = E.projection_rhs(eg, spec["k"], seed=1)
+            cols = 1
+            t0 = time.perf_counter()
+            done = 0
+            while time.perf_counter() - t0 < budget_s and done < Y.shape[1]:
+                R.cg(L, Y[:, done:done + cols], tol=spec["tol"])
+                done += cols
+                cols = min(cols * 2, 16)
+            dt = time.perf_counter() - t0
+            return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",
+                    "sample": f"first {done} of the {spec['k']} projection right-hand sides, "
+                              f"oracle Jacobi-PCG (FP64) to rel. residual {spec['tol']:g}, {dt:.1f} s"}
+        n = eg.n
+        rng = np.random.default_rng(1)
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < budget_s and done < 4096:
+            s = rng.integers(0, n, 4)
+            t = (s + 1 + rng.integers(0, n - 1, 4)) % n
+            R.resistance_cg(L, s, t, tol=spec["tol"])
+            done += 4
+        dt = time.perf_counter() - t0
+        return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",
+                "sample": f"{done} pair right-hand sides e_s - e_t, oracle Jacobi-PCG (FP64) to "
+                          f"rel. residual {spec['tol']:g}, {dt:.1f} s"}
+    finally:
+        if ctxm:
+            ctxm.__exit__(None, None, None)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ba100k_jl512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the path would shard right-hand-side columns across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    os.environ.setdefault("CFC_PROFILE", "1")
+    os.environ.setdefault("CFC_PROFILE_KERNEL", DOMINANT)
+    import numpy as np
+    import torch
+
+    if args.calibrate_copy:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copies": 5}))
+        return
+
+    import paper_1607_02955_amd as cfc
+    import synth
+
+    eg, spec = make_workload(args.workload)
+    ctx = cfc.Context(0)
+    g = cfc.Graph.from_edgelist(ctx, eg)
+    t0 = time.perf_counter()
+    g.build_hierarchy()
+    setup_s = time.perf_counter() - t0
+    info = g.info()
+    nodes = synth.query_nodes(eg.n, spec["queries"], seed=1)
+    prec = spec.get("precision", 0)
+    kw = dict(tol=spec["tol"], block=spec["block"], precision=prec)
+
+    def step(seed):
+        if spec["kind"] == "jl":
+            st = g.jl_sketch(spec["k"], seed=seed, stats=True, **kw)
+            g.farness_jl(nodes)
+            return st, spec["k"]
+        if spec["kind"] == "sampling":
+            _, _, st = g.farness_sampling(nodes, spec["k"], seed=seed, stats=True, **kw)
+            return st, st["columns"]
+        _, _, st = g.farness_exact(nodes, stats=True, **kw)
+        return st, st["columns"]
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    agg = {"cols": 0, "iters": 0, "refine": 0, "bytes": 0.0, "kms": 0.0, "kbytes": 0.0, "kl": 0,
+           "solve_ms": 0.0, "maxrel": 0.0, "W": 0}
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st, cols = step(1 + i)
+        agg["cols"] += cols
+        agg["iters"] += st["inner_iters"]
+        agg["refine"] += st["refine_steps"]
+        agg["bytes"] += st["model_bytes"]
+        agg["kms"] += st["spmm_ms"]
+        agg["kbytes"] += st["spmm_bytes"]
+        agg["kl"] += st["spmm_launches"]
+        agg["solve_ms"] += st["solve_ms"]
+        agg["maxrel"] = max(agg["maxrel"], st["max_rel_residual"])
+        agg["W"] = st["block_width"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = agg["cols"] / dt
+    workload = args.workload
+    roof = None
+    if agg["kl"]:
+        per_launch = agg["kbytes"] / agg["kl"]
+        avg_ms = agg["kms"] / agg["kl"]
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(workload, DOMINANT, per_launch),
+                "kernel": KERNEL_NAMES[DOMINANT], "avg_launch_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": per_launch, "launches": agg["kl"]}
+    out = {
+        "metric": "solved RHS/s at 1e-6 rel. residual", "value": round(value, 2),
+        "unit": "solved RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if prec == 0 else "f64", "data": "synthetic",
+        "config": {"workload": workload, "graph": eg.name, "n": eg.n, "m": eg.m,
+                   "estimator": spec["kind"], "k": spec.get("k"), "block_width": agg["W"],
+                   "tol": spec["tol"], "query_nodes": spec["queries"], "levels": info["levels"],
+                   "operator_complexity": round(info["operator_complexity"], 3)},
+        "roofline": roof,
+        "solve": {"pcg_iters_per_step": agg["iters"] / args.steps,
+                  "refine_steps_per_step": agg["refine"] / args.steps,
+                  "max_rel_residual": agg["maxrel"],
+                  "model_bytes_per_step": agg["bytes"] / args.steps,
+                  "whole_path_hbm_frac": round(agg["bytes"] / (dt * 1e9) / HBM_PEAK_GBS, 4),
+                  "setup_s": round(setup_s, 3)},
+    }
+    if not args.no_fp64_baseline:
+        # the plain FP64 one-right-hand-side-at-a-time GPU solve on the same
+        # hierarchy: 8 pair right-hand sides
+        rng = np.random.default_rng(5)
+        s = rng.integers(0, eg.n, 8)
+        t = (s + 1 + rng.integers(0, eg.n - 1, 8)) % eg.n
+        g.resistance(s[:1], t[:1], block=1, precision=1, tol=spec["tol"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st1 = g.resistance(s, t, block=1, precision=1, tol=spec["tol"], stats=True)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - t1
+        out["fp64_one_rhs_gpu"] = {"value": round(8 / d1, 2), "unit": "solved RHS/s",
+                                   "pcg_iters_per_rhs": st1["inner_iters"] / 8,
+                                   "speedup_of_batched": round(value / (8 / d1), 2)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(eg, spec, args.cpu_budget)
+        out["cpu_baseline"]["host"] = os.uname().nodename
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -188,7 +188,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
                         1, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
       g_rr = g_cs = grid_for(d0.n, k.rg);
-      bytes += d0.n * nw * (first_x ? 4 : 6);
+      bytes += d0.n * nw * (first_x ? 5 : 6);
     }
     k.coarse(g->D->nc, (g->D->nc + 15) / 16 * 16, g->D->cpinv.as<double>(), rsrc, w.z.p, s);
     k.dot(d0.n, rsrc, w.z.p, w.part_ptr(P_RZ), s);
@@ -196,11 +196,16 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     bytes += d0.n * nw * 3 + 8.0 * d0.n * d0.n;
     return;
   }
+  if (update) prof_begin(K_RESTRICT0);
   k.update_restrict(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.b[1].p, w.scal.as<double>(),
                     first_x, update ? 1 : 0, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
-  if (update) g_rr = g_cs = grid_for(d0.nagg, k.rg);
-  bytes += d0.n * nw * (update ? (first_x ? 4 : 6) : 1) + d0.nagg * nw +
-           mat_bytes(d0, !d0.unit, es) + 4.0 * (d0.nagg + 1);
+  const double rb = d0.n * nw * (update ? (first_x ? 5 : 6) : 1) + d0.nagg * nw +
+                    mat_bytes(d0, !d0.unit, es) + 4.0 * (d0.nagg + 1);
+  if (update) {
+    prof_end(K_RESTRICT0, rb);
+    g_rr = g_cs = grid_for(d0.nagg, k.rg);
+  }
+  bytes += rb;
   for (int l = 1; l + 1 < L; ++l) {
     const DevLevel& d = g->D->lv[l];
     k.restrict_(w.la[l], w.b[l].p, w.b[l + 1].p, s);
@@ -376,7 +381,9 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so) : g(&gr), p
   const char* pe = std::getenv("CFC_PROFILE");
   profile = pe && pe[0] == '1';
   const char* pk = std::getenv("CFC_PROFILE_KERNEL");
-  prof_kernel = (pk && std::strcmp(pk, "prolong") == 0) ? K_PROLONG0 : K_SPMM;
+  prof_kernel = K_SPMM;
+  if (pk && std::strcmp(pk, "prolong") == 0) prof_kernel = K_PROLONG0;
+  if (pk && std::strcmp(pk, "restrict") == 0) prof_kernel = K_RESTRICT0;
   ws = &get_workspace(*g, p.block, p.precision == CFC_PREC_FP64, stream);
   CFC_HIP(hipEventCreate(&ev0));
   CFC_HIP(hipEventCreate(&ev1));

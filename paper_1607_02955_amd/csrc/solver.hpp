@@ -8,7 +8,7 @@
 namespace cfc {
 
 enum PartSlot { P_PQ = 0, P_RZ, P_RR, P_CS, P_COUNT };
-enum ProfKernel { K_SPMM = 0, K_PROLONG0 = 1 };
+enum ProfKernel { K_SPMM = 0, K_PROLONG0 = 1, K_RESTRICT0 = 2 };
 
 // Device buffers for solving one block of W columns in one precision.
 struct Workspace {
