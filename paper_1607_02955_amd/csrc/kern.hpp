@@ -23,6 +23,7 @@ struct LevelArgs {
   const int* aggptr = nullptr;// [nagg+1] aggregate row ranges
   double omega = 2.0 / 3.0;
   double mu = 1.5;
+  int split = 1;    // row groups sharing each row / aggregate: 1, 4 or 16
 };
 
 // Right-hand side of the FP64 residual kernel.
@@ -40,6 +41,9 @@ struct KernTable {
   int W = 0;
   int esize = 0;  // sizeof(T)
   int rg = 0;     // rows (row groups) per workgroup
+  // workgroups per column slice (= rows of partial sums) of a kernel over
+  // `units` units of the level
+  int (*rows_grid)(const LevelArgs&, int units);
   // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q
   void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, const double* scal,
                   int first, double* part, hipStream_t);

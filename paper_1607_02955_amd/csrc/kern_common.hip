@@ -38,12 +38,33 @@ int grid_for(int units, int rg) {
 namespace {
 
 // Sum partial rows g = 0..G-1 of up to three arrays, per column, in a fixed
-// order, then apply the scalar update of the PCG / refinement step.
+// order, then apply the scalar update of the PCG / refinement step.  A
+// workgroup owns FCH columns; each of its 256/FCH thread groups takes every
+// (256/FCH)-th partial row (four loads in flight), and LDS combines the
+// groups in order.
+constexpr int FCH = 16;
+
+__device__ __forceinline__ double sum_rows(const double* __restrict__ p, int G, int W, int c, int sp,
+                                           int S) {
+  double s = 0;
+  int g = sp;
+  for (; g + 3 * S < G; g += 4 * S) {
+    const double a0 = p[(size_t)g * W + c], a1 = p[(size_t)(g + S) * W + c];
+    const double a2 = p[(size_t)(g + 2 * S) * W + c], a3 = p[(size_t)(g + 3 * S) * W + c];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; g < G; g += S) s += p[(size_t)g * W + c];
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_finalize(int W, int op, int g0, const double* __restrict__ p0,
                                                   int g1, const double* __restrict__ p1, int g2,
                                                   const double* __restrict__ p2,
                                                   double* __restrict__ scal) {
-  const int CH = W < 64 ? W : 64;
+  const int CH = W < FCH ? W : FCH;
   const int S = 256 / CH;
   const int tid = threadIdx.x;
   const int c = blockIdx.x * CH + tid % CH;
@@ -51,11 +72,9 @@ __global__ __launch_bounds__(256) void k_finalize(int W, int op, int g0, const d
   __shared__ double red[3][256];
   double s0 = 0, s1 = 0, s2 = 0;
   if (sp < S && c < W) {
-    for (int g = sp; g < g0; g += S) s0 += p0[(size_t)g * W + c];
-    if (p1)
-      for (int g = sp; g < g1; g += S) s1 += p1[(size_t)g * W + c];
-    if (p2)
-      for (int g = sp; g < g2; g += S) s2 += p2[(size_t)g * W + c];
+    s0 = sum_rows(p0, g0, W, c, sp, S);
+    if (p1) s1 = sum_rows(p1, g1, W, c, sp, S);
+    if (p2) s2 = sum_rows(p2, g2, W, c, sp, S);
   }
   red[0][tid] = s0;
   red[1][tid] = s1;
@@ -165,7 +184,7 @@ void zero_fill(void* p, size_t bytes, hipStream_t s) {
 
 void finalize(int W, int op, int g0, const double* p0, int g1, const double* p1, int g2,
               const double* p2, double* scal, hipStream_t s) {
-  const int CH = W < 64 ? W : 64;
+  const int CH = W < FCH ? W : FCH;
   hipLaunchKernelGGL(k_finalize, dim3((W + CH - 1) / CH), dim3(256), 0, s, W, op, g0, p0, g1, p1,
                      g2, p2, scal);
 }

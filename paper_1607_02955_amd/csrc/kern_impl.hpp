@@ -1,12 +1,14 @@
 // Device kernels of the multigrid Laplacian solve (gfx950, wave64).
 //
 // Data layout: every n x W block is node-major (node u's W values are
-// contiguous).  A "row group" of LPR lanes owns one row at a time, each lane
-// V consecutive columns (W = LPR * V), so a neighbour's row is one coalesced
-// W*sizeof(T)-byte read.  Workgroups walk a contiguous range of row tiles,
-// and the tile ranges are dealt out XCD by XCD (hardware deals workgroups to
-// the 8 XCDs round-robin), so rows that are close in the aggregate-nested
-// numbering share an L2.
+// contiguous).  The W columns are split into NS slices of WS = W / NS
+// columns and workgroup b works on slice b mod NS: the hardware deals
+// workgroups to the 8 XCDs round-robin, so with NS = 8 each XCD touches only
+// its own column slice of every gathered row and its private L2 holds 1/8 of
+// the block.  Inside a slice a "row group" of LPR lanes owns one row at a
+// time, each lane V consecutive columns (WS = LPR * V), so a neighbour's
+// slice row is one coalesced WS*sizeof(T)-byte read.  The row groups of a
+// workgroup walk a contiguous range of row tiles.
 //
 // The operator is the graph Laplacian L = D - A (Sec. 2); the smoother is
 // weighted Jacobi S = omega D^-1; P is piecewise constant over aggregates.
@@ -25,13 +27,23 @@
 namespace cfc {
 namespace dev {
 
-template <int W> struct Shape;
-template <> struct Shape<1> { static constexpr int LPR = 1, V = 1; };
-template <> struct Shape<32> { static constexpr int LPR = 8, V = 4; };
-template <> struct Shape<64> { static constexpr int LPR = 16, V = 4; };
-template <> struct Shape<128> { static constexpr int LPR = 32, V = 4; };
-template <> struct Shape<256> { static constexpr int LPR = 64, V = 4; };
-template <> struct Shape<512> { static constexpr int LPR = 64, V = 8; };
+// Column slicing and lane shape of a W-wide block.
+template <int W> struct Shape {
+  static constexpr int NS = W >= 32 ? 8 : 1;  // column slices (one per XCD)
+  static constexpr int WS = W / NS;           // columns per slice
+  static constexpr int V = WS >= 4 ? 4 : 1;   // columns per lane
+  static constexpr int LPR = WS / V;          // lanes per row group
+  static constexpr int RG = kBlock / LPR;     // row groups per workgroup
+};
+
+// Slice of this workgroup and its index among the workgroups of that slice.
+template <int W>
+__device__ __forceinline__ void slice_of_block(int& slice, int& rb, int& grb) {
+  constexpr int NS = Shape<W>::NS;
+  slice = blockIdx.x % NS;
+  rb = blockIdx.x / NS;
+  grb = gridDim.x / NS;
+}
 
 template <typename T, int V>
 struct alignas((sizeof(T) * V) >= 16 ? 16 : sizeof(T) * V) Vec {
@@ -47,26 +59,25 @@ __device__ __forceinline__ void st(T* p, const Vec<T, V>& x) {
   *reinterpret_cast<Vec<T, V>*>(p) = x;
 }
 
-// Contiguous tile range of this workgroup; consecutive ranges go to one XCD.
-__device__ __forceinline__ void block_tiles(int ntiles, int& tb, int& te) {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int vb = ((G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+// Contiguous range of row tiles for row-block rb of G row-blocks.
+__device__ __forceinline__ void block_tiles(int ntiles, int rb, int G, int& tb, int& te) {
   const int per = (ntiles + G - 1) / G;
-  tb = min(vb * per, ntiles);
+  tb = min(rb * per, ntiles);
   te = min(tb + per, ntiles);
 }
 
-// Sum acc over the row groups of the workgroup and store W values to out.
+// Sum acc over the row groups of the workgroup and store the WS slice
+// columns to out (which points at the slice's first column).
 template <int W>
 __device__ __forceinline__ void block_store(const double* acc, double* lds, double* out) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
 #pragma unroll
-  for (int i = 0; i < V; ++i) lds[rg * W + c0 + i] = acc[i];
+  for (int i = 0; i < V; ++i) lds[rg * WS + c0 + i] = acc[i];
   __syncthreads();
-  for (int c = threadIdx.x; c < W; c += kBlock) {
+  for (int c = threadIdx.x; c < WS; c += kBlock) {
     double s = 0;
-    for (int g = 0; g < RG; ++g) s += lds[g * W + c];
+    for (int g = 0; g < RG; ++g) s += lds[g * WS + c];
     out[c] = s;
   }
   __syncthreads();
@@ -77,46 +88,79 @@ __device__ __forceinline__ T wt(const T* w, int e) {
   return w ? w[e] : T(1);
 }
 
-// a -= sum_e w_e x[col_e]   (rows e0..e1), four gathers in flight.
-template <typename T, int W>
-__device__ __forceinline__ void gather_sub(T* a, const T* __restrict__ x, const int* __restrict__ col,
-                                           const T* __restrict__ w, int e0, int e1, int c0) {
+// nb += sum over edges e = e0 + s, e0 + s + S, ... < e1 of w_e * f(col_e),
+// four neighbour rows in flight.  f returns the neighbour's WS-slice values.
+template <typename T, int W, class F>
+__device__ __forceinline__ void gather_acc(T* nb, const int* __restrict__ col, const T* __restrict__ w,
+                                           int e0, int e1, int s, int S, F&& f) {
   constexpr int V = Shape<W>::V;
-  int e = e0;
-  for (; e + 4 <= e1; e += 4) {
-    const int v0 = col[e], v1 = col[e + 1], v2 = col[e + 2], v3 = col[e + 3];
-    const T w0 = wt(w, e), w1 = wt(w, e + 1), w2 = wt(w, e + 2), w3 = wt(w, e + 3);
-    const Vec<T, V> x0 = ld<T, V>(x + (size_t)v0 * W + c0);
-    const Vec<T, V> x1 = ld<T, V>(x + (size_t)v1 * W + c0);
-    const Vec<T, V> x2 = ld<T, V>(x + (size_t)v2 * W + c0);
-    const Vec<T, V> x3 = ld<T, V>(x + (size_t)v3 * W + c0);
+  int e = e0 + s;
+  for (; e + 3 * S < e1; e += 4 * S) {
+    const int v0 = col[e], v1 = col[e + S], v2 = col[e + 2 * S], v3 = col[e + 3 * S];
+    const T w0 = wt(w, e), w1 = wt(w, e + S), w2 = wt(w, e + 2 * S), w3 = wt(w, e + 3 * S);
+    const Vec<T, V> x0 = f(v0), x1 = f(v1), x2 = f(v2), x3 = f(v3);
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      a[i] -= w0 * x0.v[i];
-      a[i] -= w1 * x1.v[i];
-      a[i] -= w2 * x2.v[i];
-      a[i] -= w3 * x3.v[i];
+      nb[i] += w0 * x0.v[i];
+      nb[i] += w1 * x1.v[i];
+      nb[i] += w2 * x2.v[i];
+      nb[i] += w3 * x3.v[i];
     }
   }
-  for (; e < e1; ++e) {
+  for (; e < e1; e += S) {
     const int v0 = col[e];
     const T w0 = wt(w, e);
-    const Vec<T, V> x0 = ld<T, V>(x + (size_t)v0 * W + c0);
+    const Vec<T, V> x0 = f(v0);
 #pragma unroll
-    for (int i = 0; i < V; ++i) a[i] -= w0 * x0.v[i];
+    for (int i = 0; i < V; ++i) nb[i] += w0 * x0.v[i];
   }
+}
+
+// Split decomposition: SPLIT row groups share each unit (row or aggregate),
+// each taking every SPLIT-th edge; a tile holds RG / SPLIT units.  After the
+// gathers, wg_combine hands each unit's leading row group (split 0) the sum
+// over its SPLIT groups, in a fixed order.
+template <int W, int SPLIT>
+struct Deco {
+  static_assert(Shape<W>::RG % SPLIT == 0, "split must divide the row groups");
+  static constexpr int PER_TILE = Shape<W>::RG / SPLIT;
+  __device__ static int unit(int t, int rg) { return t * PER_TILE + rg / SPLIT; }
+  __device__ static int split(int rg) { return rg % SPLIT; }
+  __device__ static bool leader(int rg) { return rg % SPLIT == 0; }
+};
+
+template <typename T, int W, int SPLIT>
+__device__ __forceinline__ void wg_combine(T* nb, T* lds) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, WS = Shape<W>::WS;
+  const int rg = threadIdx.x / LPR, c = (threadIdx.x % LPR) * V;
+#pragma unroll
+  for (int i = 0; i < V; ++i) lds[rg * WS + c + i] = nb[i];
+  __syncthreads();
+  if (rg % SPLIT == 0) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      T s = 0;
+      for (int g = 0; g < SPLIT; ++g) s += lds[(rg + g) * WS + c + i];
+      nb[i] = s;
+    }
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // PCG step on level 0: q = L z + beta q, p = z + beta p; partial p.q
-template <typename T, int W>
+template <typename T, int W, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __restrict__ z,
                                                     T* __restrict__ p, T* __restrict__ q,
                                                     const double* __restrict__ scal, int first,
                                                     double* __restrict__ part) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  __shared__ double lds[RG * W];
-  const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  using D = Deco<W, SPLIT>;
+  __shared__ double lds[RG * WS];
+  __shared__ T ldc[SPLIT > 1 ? RG * WS : 1];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* w = static_cast<const T*>(L.w);
   const T* deg = static_cast<const T*>(L.deg);
   T beta[V];
@@ -127,28 +171,31 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
     acc[i] = 0;
   }
   int tb, te;
-  block_tiles((L.n + RG - 1) / RG, tb, te);
+  block_tiles((L.n + D::PER_TILE - 1) / D::PER_TILE, rb, grb, tb, te);
   for (int t = tb; t < te; ++t) {
-    const int u = t * RG + rg;
-    if (u < L.n) {
+    const int u = D::unit(t, rg);
+    T nb[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) nb[i] = 0;
+    if (u < L.n)
+      gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT,
+                       [&](int v) { return ld<T, V>(z + (size_t)v * W + c0); });
+    if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(nb, ldc);
+    if (u < L.n && D::leader(rg)) {
       const size_t o = (size_t)u * W + c0;
       const Vec<T, V> zu = ld<T, V>(z + o);
-      T a[V];
       const T du = deg[u];
-#pragma unroll
-      for (int i = 0; i < V; ++i) a[i] = du * zu.v[i];
-      gather_sub<T, W>(a, z, L.col, w, L.rowptr[u], L.rowptr[u + 1], c0);
       Vec<T, V> pn, qn;
       if (first) {
         pn = zu;
 #pragma unroll
-        for (int i = 0; i < V; ++i) qn.v[i] = a[i];
+        for (int i = 0; i < V; ++i) qn.v[i] = du * zu.v[i] - nb[i];
       } else {
         const Vec<T, V> po = ld<T, V>(p + o), qo = ld<T, V>(q + o);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
           pn.v[i] = zu.v[i] + beta[i] * po.v[i];
-          qn.v[i] = a[i] + beta[i] * qo.v[i];
+          qn.v[i] = (du * zu.v[i] - nb[i]) + beta[i] * qo.v[i];
         }
       }
       st<T, V>(p + o, pn);
@@ -157,20 +204,27 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
       for (int i = 0; i < V; ++i) acc[i] += double(pn.v[i]) * double(qn.v[i]);
     }
   }
-  block_store<W>(acc, lds, part + (size_t)blockIdx.x * W);
+  block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // ---------------------------------------------------------------------------
-// Update (r -= alpha q, x += alpha p) and/or pre-smooth + residual + restrict.
-// Units are aggregates when RESTRICT (their rows are contiguous), else rows.
-template <typename T, int W, bool UPDATE, bool RESTRICT>
+// Update (r -= alpha q, x += alpha p) and/or pre-smooth + residual + restrict:
+// bc[I] = sum_{u in I} (b - L S b)_u with b = r_out, which, the rows of an
+// aggregate being contiguous, is (1 - omega) sum_{u in I} b_u plus the sum,
+// over every edge leaving a row of I, of w_e * omega / D_vv * b_v.
+// Units are aggregates when RESTRICT, else rows.
+template <typename T, int W, bool UPDATE, bool RESTRICT, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_update_restrict(
     LevelArgs L, const T* __restrict__ r_in, const T* __restrict__ q, const T* __restrict__ p,
     T* __restrict__ x, T* __restrict__ r_out, T* __restrict__ bc, const double* __restrict__ scal,
     int first, double* __restrict__ part_rr, double* __restrict__ part_cs) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  __shared__ double lds[RG * W];
-  const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  using D = Deco<W, SPLIT>;
+  __shared__ double lds[UPDATE ? RG * WS : 1];
+  __shared__ T ldc[SPLIT > 1 ? RG * WS : 1];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* w = static_cast<const T*>(L.w);
   const T* sd = static_cast<const T*>(L.sd);
   const T om1 = T(1.0 - L.omega);
@@ -184,97 +238,80 @@ __global__ __launch_bounds__(kBlock) void k_update_restrict(
   }
   const int units = RESTRICT ? L.nagg : L.n;
   int tb, te;
-  block_tiles((units + RG - 1) / RG, tb, te);
+  block_tiles((units + D::PER_TILE - 1) / D::PER_TILE, rb, grb, tb, te);
   for (int t = tb; t < te; ++t) {
-    const int I = t * RG + rg;
-    if (I >= units) continue;
-    const int r0 = RESTRICT ? L.aggptr[I] : I;
-    const int r1 = RESTRICT ? L.aggptr[I + 1] : I + 1;
+    const int I = D::unit(t, rg);
+    const bool valid = I < units;
     T s[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) s[i] = 0;
-    for (int u = r0; u < r1; ++u) {
-      const size_t o = (size_t)u * W + c0;
-      Vec<T, V> rn = ld<T, V>(r_in + o);
-      if (UPDATE) {
-        const Vec<T, V> qu = ld<T, V>(q + o), pu = ld<T, V>(p + o);
-        Vec<T, V> xu;
-        if (!first) xu = ld<T, V>(x + o);
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          rn.v[i] -= alpha[i] * qu.v[i];
-          xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
-          rr[i] += double(rn.v[i]) * double(rn.v[i]);
-          cs[i] += double(xu.v[i]);
-        }
-        st<T, V>(x + o, xu);
-        st<T, V>(r_out + o, rn);
-      }
-      if (RESTRICT) {
-        T a[V];
-#pragma unroll
-        for (int i = 0; i < V; ++i) a[i] = om1 * rn.v[i];
-        const int e1 = L.rowptr[u + 1];
-        int e = L.rowptr[u];
-        for (; e + 2 <= e1; e += 2) {
-          const int v0 = L.col[e], v1 = L.col[e + 1];
-          const T f0 = wt(w, e) * sd[v0], f1 = wt(w, e + 1) * sd[v1];
-          Vec<T, V> a0 = ld<T, V>(r_in + (size_t)v0 * W + c0);
-          Vec<T, V> a1 = ld<T, V>(r_in + (size_t)v1 * W + c0);
-          if (UPDATE) {
-            const Vec<T, V> q0 = ld<T, V>(q + (size_t)v0 * W + c0);
-            const Vec<T, V> q1 = ld<T, V>(q + (size_t)v1 * W + c0);
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-              a0.v[i] -= alpha[i] * q0.v[i];
-              a1.v[i] -= alpha[i] * q1.v[i];
-            }
-          }
+    if (valid) {
+      const int r0 = RESTRICT ? L.aggptr[I] : I;
+      const int r1 = RESTRICT ? L.aggptr[I + 1] : I + 1;
+      for (int u = r0 + D::split(rg); u < r1; u += SPLIT) {
+        const size_t o = (size_t)u * W + c0;
+        Vec<T, V> rn = ld<T, V>(r_in + o);
+        if (UPDATE) {
+          const Vec<T, V> qu = ld<T, V>(q + o), pu = ld<T, V>(p + o);
+          Vec<T, V> xu;
+          if (!first) xu = ld<T, V>(x + o);
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            a[i] += f0 * a0.v[i];
-            a[i] += f1 * a1.v[i];
+            rn.v[i] -= alpha[i] * qu.v[i];
+            xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
+            rr[i] += double(rn.v[i]) * double(rn.v[i]);
+            cs[i] += double(xu.v[i]);
           }
-        }
-        if (e < e1) {
-          const int v0 = L.col[e];
-          const T f0 = wt(w, e) * sd[v0];
-          Vec<T, V> a0 = ld<T, V>(r_in + (size_t)v0 * W + c0);
-          if (UPDATE) {
-            const Vec<T, V> q0 = ld<T, V>(q + (size_t)v0 * W + c0);
-#pragma unroll
-            for (int i = 0; i < V; ++i) a0.v[i] -= alpha[i] * q0.v[i];
-          }
-#pragma unroll
-          for (int i = 0; i < V; ++i) a[i] += f0 * a0.v[i];
+          st<T, V>(x + o, xu);
+          st<T, V>(r_out + o, rn);
         }
 #pragma unroll
-        for (int i = 0; i < V; ++i) s[i] += a[i];
+        for (int i = 0; i < V; ++i) s[i] += om1 * rn.v[i];
       }
+      if (RESTRICT)
+        gather_acc<T, W>(s, L.col, w, L.rowptr[r0], L.rowptr[r1], D::split(rg), SPLIT, [&](int v) {
+          Vec<T, V> r = ld<T, V>(r_in + (size_t)v * W + c0);
+          const T f = sd[v];
+          if (UPDATE) {
+            const Vec<T, V> qv = ld<T, V>(q + (size_t)v * W + c0);
+#pragma unroll
+            for (int i = 0; i < V; ++i) r.v[i] -= alpha[i] * qv.v[i];
+          }
+#pragma unroll
+          for (int i = 0; i < V; ++i) r.v[i] *= f;
+          return r;
+        });
     }
     if (RESTRICT) {
-      Vec<T, V> sv;
+      if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(s, ldc);
+      if (valid && D::leader(rg)) {
+        Vec<T, V> sv;
 #pragma unroll
-      for (int i = 0; i < V; ++i) sv.v[i] = s[i];
-      st<T, V>(bc + (size_t)I * W + c0, sv);
+        for (int i = 0; i < V; ++i) sv.v[i] = s[i];
+        st<T, V>(bc + (size_t)I * W + c0, sv);
+      }
     }
   }
   if (UPDATE) {
-    block_store<W>(rr, lds, part_rr + (size_t)blockIdx.x * W);
-    block_store<W>(cs, lds, part_cs + (size_t)blockIdx.x * W);
+    block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
+    block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Prolongation + post-smoothing: xt = S b + mu xc[agg], x = xt + S (b - L xt).
-template <typename T, int W, bool DOT>
+template <typename T, int W, bool DOT, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T* __restrict__ b,
                                                            const T* __restrict__ xc,
                                                            T* __restrict__ x,
                                                            double* __restrict__ part) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  __shared__ double lds[DOT ? RG * W : 1];
-  const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  using D = Deco<W, SPLIT>;
+  __shared__ double lds[DOT ? RG * WS : 1];
+  __shared__ T ldc[SPLIT > 1 ? RG * WS : 1];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* w = static_cast<const T*>(L.w);
   const T* sd = static_cast<const T*>(L.sd);
   const T* deg = static_cast<const T*>(L.deg);
@@ -283,54 +320,40 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = 0;
   int tb, te;
-  block_tiles((L.n + RG - 1) / RG, tb, te);
+  block_tiles((L.n + D::PER_TILE - 1) / D::PER_TILE, rb, grb, tb, te);
   for (int t = tb; t < te; ++t) {
-    const int u = t * RG + rg;
-    if (u >= L.n) continue;
-    const size_t o = (size_t)u * W + c0;
-    const Vec<T, V> bu = ld<T, V>(b + o);
-    const Vec<T, V> cu = ld<T, V>(xc + (size_t)L.agg[u] * W + c0);
-    const T sdu = sd[u], du = deg[u];
-    T xt[V], a[V];
+    const int u = D::unit(t, rg);
+    T nb[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      xt[i] = sdu * bu.v[i] + mu * cu.v[i];
-      a[i] = du * xt[i];
-    }
-    const int e1 = L.rowptr[u + 1];
-    int e = L.rowptr[u];
-    for (; e + 2 <= e1; e += 2) {
-      const int v0 = L.col[e], v1 = L.col[e + 1];
-      const T w0 = wt(w, e), w1 = wt(w, e + 1);
-      const T s0 = sd[v0], s1 = sd[v1];
-      const int g0 = L.agg[v0], g1 = L.agg[v1];
-      const Vec<T, V> b0 = ld<T, V>(b + (size_t)v0 * W + c0);
-      const Vec<T, V> b1 = ld<T, V>(b + (size_t)v1 * W + c0);
-      const Vec<T, V> x0 = ld<T, V>(xc + (size_t)g0 * W + c0);
-      const Vec<T, V> x1 = ld<T, V>(xc + (size_t)g1 * W + c0);
+    for (int i = 0; i < V; ++i) nb[i] = 0;
+    if (u < L.n)
+      gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT, [&](int v) {
+        const T sv = sd[v];
+        const Vec<T, V> bv = ld<T, V>(b + (size_t)v * W + c0);
+        const Vec<T, V> xv = ld<T, V>(xc + (size_t)L.agg[v] * W + c0);
+        Vec<T, V> r;
+#pragma unroll
+        for (int i = 0; i < V; ++i) r.v[i] = sv * bv.v[i] + mu * xv.v[i];
+        return r;
+      });
+    if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(nb, ldc);
+    if (u < L.n && D::leader(rg)) {
+      const size_t o = (size_t)u * W + c0;
+      const Vec<T, V> bu = ld<T, V>(b + o);
+      const Vec<T, V> cu = ld<T, V>(xc + (size_t)L.agg[u] * W + c0);
+      const T sdu = sd[u], du = deg[u];
+      Vec<T, V> xo;
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        a[i] -= w0 * (s0 * b0.v[i] + mu * x0.v[i]);
-        a[i] -= w1 * (s1 * b1.v[i] + mu * x1.v[i]);
+        const T xt = sdu * bu.v[i] + mu * cu.v[i];
+        const T lx = du * xt - nb[i];
+        xo.v[i] = xt + sdu * (bu.v[i] - lx);
+        if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
       }
+      st<T, V>(x + o, xo);
     }
-    if (e < e1) {
-      const int v0 = L.col[e];
-      const T w0 = wt(w, e), s0 = sd[v0];
-      const Vec<T, V> b0 = ld<T, V>(b + (size_t)v0 * W + c0);
-      const Vec<T, V> x0 = ld<T, V>(xc + (size_t)L.agg[v0] * W + c0);
-#pragma unroll
-      for (int i = 0; i < V; ++i) a[i] -= w0 * (s0 * b0.v[i] + mu * x0.v[i]);
-    }
-    Vec<T, V> xo;
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      xo.v[i] = xt[i] + sdu * (bu.v[i] - a[i]);
-      if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
-    }
-    st<T, V>(x + o, xo);
   }
-  if (DOT) block_store<W>(acc, lds, part + (size_t)blockIdx.x * W);
+  if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // ---------------------------------------------------------------------------
@@ -381,33 +404,40 @@ __global__ __launch_bounds__(256) void k_coarse_simple(int nc, int ncp, const do
 template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const T* __restrict__ a, const T* __restrict__ b,
                                                 double* __restrict__ part) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  __shared__ double lds[RG * W];
-  const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[RG * WS];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   double acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = 0;
   int tb, te;
-  block_tiles((n + RG - 1) / RG, tb, te);
+  block_tiles((n + RG - 1) / RG, rb, grb, tb, te);
   for (int t = tb; t < te; ++t) {
     const int u = t * RG + rg;
     if (u >= n) continue;
-    const Vec<T, V> x = ld<T, V>(a + (size_t)u * W + c0), y = ld<T, V>(b + (size_t)u * W + c0);
+    const Vec<T, V> x = ld<T, V>(a + (size_t)u * W + c0);
+    const Vec<T, V> y = b ? ld<T, V>(b + (size_t)u * W + c0) : Vec<T, V>{};
 #pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] += double(x.v[i]) * double(y.v[i]);
+    for (int i = 0; i < V; ++i) acc[i] += b ? double(x.v[i]) * double(y.v[i]) : double(x.v[i]);
   }
-  block_store<W>(acc, lds, part + (size_t)blockIdx.x * W);
+  block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 residual r = b - L x (Eq. 1), stored as TO; partial |r|^2 (FP64).
-template <typename TO, int W>
+template <typename TO, int W, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double* __restrict__ x,
                                                        RhsArgs rhs, TO* __restrict__ r_out,
                                                        double* __restrict__ part) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  __shared__ double lds[RG * W];
-  const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  using D = Deco<W, SPLIT>;
+  __shared__ double lds[RG * WS];
+  __shared__ double ldc[SPLIT > 1 ? RG * WS : 1];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const double* w = static_cast<const double*>(L.w);
   const double* deg = static_cast<const double*>(L.deg);
   int ps[V], pt[V];
@@ -419,40 +449,48 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double
     acc[i] = 0;
   }
   int tb, te;
-  block_tiles((L.n + RG - 1) / RG, tb, te);
+  block_tiles((L.n + D::PER_TILE - 1) / D::PER_TILE, rb, grb, tb, te);
   for (int t = tb; t < te; ++t) {
-    const int u = t * RG + rg;
-    if (u >= L.n) continue;
-    const size_t o = (size_t)u * W + c0;
-    double a[V];
+    const int u = D::unit(t, rg);
+    double nb[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) a[i] = 0;
-    if (x) {
-      const Vec<double, V> xu = ld<double, V>(x + o);
-      const double du = deg[u];
+    for (int i = 0; i < V; ++i) nb[i] = 0;
+    if (x && u < L.n)
+      gather_acc<double, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT,
+                            [&](int v) { return ld<double, V>(x + (size_t)v * W + c0); });
+    if constexpr (SPLIT > 1) wg_combine<double, W, SPLIT>(nb, ldc);
+    if (u < L.n && D::leader(rg)) {
+      const size_t o = (size_t)u * W + c0;
+      double a[V];
+      if (x) {
+        const Vec<double, V> xu = ld<double, V>(x + o);
+        const double du = deg[u];
 #pragma unroll
-      for (int i = 0; i < V; ++i) a[i] = du * xu.v[i];
-      gather_sub<double, W>(a, x, L.col, w, L.rowptr[u], L.rowptr[u + 1], c0);
+        for (int i = 0; i < V; ++i) a[i] = du * xu.v[i] - nb[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) a[i] = 0;
+      }
+      double bv[V];
+      if (rhs.kind == 0) {
+        const Vec<double, V> bb = ld<double, V>(rhs.dense + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) bv[i] = bb.v[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) bv[i] = (u == ps[i] ? 1.0 : 0.0) - (u == pt[i] ? 1.0 : 0.0);
+      }
+      Vec<TO, V> ro;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const double r = bv[i] - a[i];
+        ro.v[i] = TO(r);
+        acc[i] += r * r;
+      }
+      st<TO, V>(r_out + o, ro);
     }
-    double bv[V];
-    if (rhs.kind == 0) {
-      const Vec<double, V> bb = ld<double, V>(rhs.dense + o);
-#pragma unroll
-      for (int i = 0; i < V; ++i) bv[i] = bb.v[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < V; ++i) bv[i] = (u == ps[i] ? 1.0 : 0.0) - (u == pt[i] ? 1.0 : 0.0);
-    }
-    Vec<TO, V> ro;
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const double r = bv[i] - a[i];
-      ro.v[i] = TO(r);
-      acc[i] += r * r;
-    }
-    st<TO, V>(r_out + o, ro);
   }
-  block_store<W>(acc, lds, part + (size_t)blockIdx.x * W);
+  block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // x64 = (first ? 0 : x64) + d - mean(d), mean(d) = cs / n.
@@ -479,14 +517,16 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_jl_rhs(LevelArgs L, const int* __restrict__ iperm,
                                                    uint64_t seed, int64_t i0, int64_t k,
                                                    double* __restrict__ Y) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const double* w = static_cast<const double*>(L.w);
   const double inv_sqrt_k = 1.0 / sqrt(double(k));
   const int64_t sys0 = i0 + c0;
   const uint64_t word = uint64_t(sys0) >> 6;
   int tb, te;
-  block_tiles((L.n + RG - 1) / RG, tb, te);
+  block_tiles((L.n + RG - 1) / RG, rb, grb, tb, te);
   for (int t = tb; t < te; ++t) {
     const int u = t * RG + rg;
     if (u >= L.n) continue;
@@ -513,19 +553,21 @@ __global__ __launch_bounds__(kBlock) void k_jl_rhs(LevelArgs L, const int* __res
   }
 }
 
-// N[u] += |x_u|^2 over the first ncols columns; partial column sums.
+// Whole-row shape (no column slicing) for per-row reductions over all W columns.
+template <int W> struct RowShape {
+  static constexpr int V = W >= 512 ? W / 64 : (W >= 4 ? 4 : 1);
+  static constexpr int LPR = W / V;
+  static constexpr int RG = kBlock / LPR;
+};
+
+// N[u] += |x_u|^2 over the first ncols columns.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_jl_rownorm(int n, const double* __restrict__ x, int ncols,
-                                                       double* __restrict__ N,
-                                                       double* __restrict__ part) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
-  __shared__ double lds[RG * W];
+                                                       double* __restrict__ N) {
+  constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
   const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
-  double acc[V];
-#pragma unroll
-  for (int i = 0; i < V; ++i) acc[i] = 0;
   int tb, te;
-  block_tiles((n + RG - 1) / RG, tb, te);
+  block_tiles((n + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
   for (int t = tb; t < te; ++t) {
     const int u = t * RG + rg;
     const bool ok = u < n;
@@ -534,15 +576,11 @@ __global__ __launch_bounds__(kBlock) void k_jl_rownorm(int n, const double* __re
       const Vec<double, V> xu = ld<double, V>(x + (size_t)u * W + c0);
 #pragma unroll
       for (int i = 0; i < V; ++i)
-        if (c0 + i < ncols) {
-          s += xu.v[i] * xu.v[i];
-          acc[i] += xu.v[i];
-        }
+        if (c0 + i < ncols) s += xu.v[i] * xu.v[i];
     }
     for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
     if (ok && lane == 0) N[u] += s;
   }
-  block_store<W>(acc, lds, part + (size_t)blockIdx.x * W);
 }
 
 // T[u] += x_u . s with s the column sums held in scal[S_CS].
@@ -550,13 +588,13 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_jl_rowdot(int n, const double* __restrict__ x, int ncols,
                                                       const double* __restrict__ scal,
                                                       double* __restrict__ Tv) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = kBlock / LPR;
+  constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
   const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
   double sc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) sc[i] = (c0 + i < ncols) ? scal[S_CS * W + c0 + i] : 0.0;
   int tb, te;
-  block_tiles((n + RG - 1) / RG, tb, te);
+  block_tiles((n + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
   for (int t = tb; t < te; ++t) {
     const int u = t * RG + rg;
     const bool ok = u < n;
@@ -577,52 +615,60 @@ inline int grid_units(int units, int rg) { return grid_for(units, rg); }
 
 template <typename T, int W>
 struct Launch {
-  static constexpr int RG = kBlock / Shape<W>::LPR;
+  static constexpr int RG = Shape<W>::RG;
+  static constexpr int NS = Shape<W>::NS;
+
+  // workgroups per slice for a kernel over `units` units of level L
+  static int rows_grid(const LevelArgs& L, int units) {
+    return grid_for(units, RG / std::min(std::max(L.split, 1), RG));
+  }
+
+#define CFC_LAUNCH(K, units, ...)                                                              \
+  do {                                                                                         \
+    const int g_ = rows_grid(L, units);                                                        \
+    if (!g_) return;                                                                           \
+    const int sp_ = std::min(std::max(L.split, 1), RG);                                        \
+    if (sp_ >= 16)                                                                             \
+      hipLaunchKernelGGL((K<__VA_ARGS__, 16>), dim3(g_ * NS), dim3(kBlock), 0, s, ARGS);       \
+    else if (sp_ >= 4)                                                                         \
+      hipLaunchKernelGGL((K<__VA_ARGS__, 4>), dim3(g_ * NS), dim3(kBlock), 0, s, ARGS);        \
+    else                                                                                       \
+      hipLaunchKernelGGL((K<__VA_ARGS__, 1>), dim3(g_ * NS), dim3(kBlock), 0, s, ARGS);        \
+  } while (0)
 
   static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, const double* scal,
                       int first, double* part, hipStream_t s) {
-    const int g = grid_units(L.n, RG);
-    if (!g) return;
-    hipLaunchKernelGGL((k_spmm_pq<T, W>), dim3(g), dim3(kBlock), 0, s, L, (const T*)z, (T*)p,
-                       (T*)q, scal, first, part);
+#define ARGS L, (const T*)z, (T*)p, (T*)q, scal, first, part
+    CFC_LAUNCH(k_spmm_pq, L.n, T, W);
+#undef ARGS
   }
   static void update_restrict(const LevelArgs& L, const void* r_in, const void* q, const void* p,
                               void* x, void* r_out, void* bc, const double* scal, int first,
                               int do_update, double* prr, double* pcs, hipStream_t s) {
     const bool R = L.nagg > 0;
-    const int g = grid_units(R ? L.nagg : L.n, RG);
-    if (!g) return;
+#define ARGS L, (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal, first, prr, pcs
     if (do_update && R)
-      hipLaunchKernelGGL((k_update_restrict<T, W, true, true>), dim3(g), dim3(kBlock), 0, s, L,
-                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal,
-                         first, prr, pcs);
+      CFC_LAUNCH(k_update_restrict, L.nagg, T, W, true, true);
     else if (do_update)
-      hipLaunchKernelGGL((k_update_restrict<T, W, true, false>), dim3(g), dim3(kBlock), 0, s, L,
-                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal,
-                         first, prr, pcs);
-    else
-      hipLaunchKernelGGL((k_update_restrict<T, W, false, true>), dim3(g), dim3(kBlock), 0, s, L,
-                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal,
-                         first, prr, pcs);
+      CFC_LAUNCH(k_update_restrict, L.n, T, W, true, false);
+    else if (R)
+      CFC_LAUNCH(k_update_restrict, L.nagg, T, W, false, true);
+#undef ARGS
   }
   static void restrict_(const LevelArgs& L, const void* b, void* bc, hipStream_t s) {
-    const int g = grid_units(L.nagg, RG);
-    if (!g) return;
-    hipLaunchKernelGGL((k_update_restrict<T, W, false, true>), dim3(g), dim3(kBlock), 0, s, L,
-                       (const T*)b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
-                       (T*)nullptr, (T*)bc, (const double*)nullptr, 0, (double*)nullptr,
-                       (double*)nullptr);
+#define ARGS L, (const T*)b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)bc, \
+             (const double*)nullptr, 0, (double*)nullptr, (double*)nullptr
+    CFC_LAUNCH(k_update_restrict, L.nagg, T, W, false, true);
+#undef ARGS
   }
   static void prolong_smooth(const LevelArgs& L, const void* b, const void* xc, void* x,
                              double* part, hipStream_t s) {
-    const int g = grid_units(L.n, RG);
-    if (!g) return;
+#define ARGS L, (const T*)b, (const T*)xc, (T*)x, part
     if (part)
-      hipLaunchKernelGGL((k_prolong_smooth<T, W, true>), dim3(g), dim3(kBlock), 0, s, L,
-                         (const T*)b, (const T*)xc, (T*)x, part);
+      CFC_LAUNCH(k_prolong_smooth, L.n, T, W, true);
     else
-      hipLaunchKernelGGL((k_prolong_smooth<T, W, false>), dim3(g), dim3(kBlock), 0, s, L,
-                         (const T*)b, (const T*)xc, (T*)x, part);
+      CFC_LAUNCH(k_prolong_smooth, L.n, T, W, false);
+#undef ARGS
   }
   static void coarse(int nc, int ncp, const double* A, const void* b, void* x, hipStream_t s) {
 #ifndef CFC_COARSE_NO_MFMA
@@ -640,15 +686,14 @@ struct Launch {
   static void dot(int n, const void* a, const void* b, double* part, hipStream_t s) {
     const int g = grid_units(n, RG);
     if (!g) return;
-    hipLaunchKernelGGL((k_dot<T, W>), dim3(g), dim3(kBlock), 0, s, n, (const T*)a, (const T*)b,
+    hipLaunchKernelGGL((k_dot<T, W>), dim3(g * NS), dim3(kBlock), 0, s, n, (const T*)a, (const T*)b,
                        part);
   }
   static void residual64(const LevelArgs& L, const double* x64, RhsArgs rhs, void* r_out,
                          double* part, hipStream_t s) {
-    const int g = grid_units(L.n, RG);
-    if (!g) return;
-    hipLaunchKernelGGL((k_residual64<T, W>), dim3(g), dim3(kBlock), 0, s, L, x64, rhs, (T*)r_out,
-                       part);
+#define ARGS L, x64, rhs, (T*)r_out, part
+    CFC_LAUNCH(k_residual64, L.n, T, W);
+#undef ARGS
   }
   static void xupdate64(int n, double* x64, const void* d, const double* scal, int first,
                         hipStream_t s) {
@@ -662,17 +707,21 @@ struct Launch {
                      double* Y, hipStream_t s) {
     const int g = grid_units(L.n, RG);
     if (!g) return;
-    hipLaunchKernelGGL((k_jl_rhs<W>), dim3(g), dim3(kBlock), 0, s, L, iperm, seed, i0, k, Y);
+    hipLaunchKernelGGL((k_jl_rhs<W>), dim3(g * NS), dim3(kBlock), 0, s, L, iperm, seed, i0, k, Y);
   }
   static void jl_rownorm(int n, const double* x64, int ncols, double* N, double* part,
                          hipStream_t s) {
-    const int g = grid_units(n, RG);
+    const int g = grid_units(n, RowShape<W>::RG);
     if (!g) return;
-    hipLaunchKernelGGL((k_jl_rownorm<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, N, part);
+    hipLaunchKernelGGL((k_jl_rownorm<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, N);
+    // column sums of the block, sliced like the other partial sums
+    const int gc = grid_units(n, RG);
+    hipLaunchKernelGGL((k_dot<double, W>), dim3(gc * NS), dim3(kBlock), 0, s, n, x64,
+                       (const double*)nullptr, part);
   }
   static void jl_rowdot(int n, const double* x64, int ncols, const double* scal, double* Tv,
                         hipStream_t s) {
-    const int g = grid_units(n, RG);
+    const int g = grid_units(n, RowShape<W>::RG);
     if (!g) return;
     hipLaunchKernelGGL((k_jl_rowdot<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, scal, Tv);
   }
@@ -683,6 +732,7 @@ struct Launch {
     t.W = W;
     t.esize = sizeof(T);
     t.rg = RG;
+    t.rows_grid = &rows_grid;
     t.spmm_pq = &spmm_pq;
     t.update_restrict = &update_restrict;
     t.restrict_ = &restrict_;

@@ -112,6 +112,14 @@ static LevelArgs level_args(const Graph& g, int l, bool fp64) {
   a.aggptr = d.aggptr.as<int>();
   a.omega = g.H.omega;
   a.mu = g.H.mu;
+  // long rows (dense coarse levels, heavy-tailed graphs): several row groups
+  // share a row; about 8 edges per row group
+  static const double per_group = [] {
+    const char* e = std::getenv("CFC_SPLIT_EDGES");
+    return e ? std::atof(e) : 8.0;
+  }();
+  const double avg = d.n > 0 ? (double)d.nnz / d.n : 0.0;
+  a.split = avg >= 16 * per_group ? 16 : (avg >= 4 * per_group ? 4 : 1);
   return a;
 }
 
@@ -187,7 +195,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       a.nagg = 0;
       k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
                         1, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
-      g_rr = g_cs = grid_for(d0.n, k.rg);
+      g_rr = g_cs = k.rows_grid(a, d0.n);
       bytes += d0.n * nw * (first_x ? 5 : 6);
     }
     k.coarse(g->D->nc, (g->D->nc + 15) / 16 * 16, g->D->cpinv.as<double>(), rsrc, w.z.p, s);
@@ -203,7 +211,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
                     mat_bytes(d0, !d0.unit, es) + 4.0 * (d0.nagg + 1);
   if (update) {
     prof_end(K_RESTRICT0, rb);
-    g_rr = g_cs = grid_for(d0.nagg, k.rg);
+    g_rr = g_cs = k.rows_grid(w.la[0], d0.nagg);
   }
   bytes += rb;
   for (int l = 1; l + 1 < L; ++l) {
@@ -223,7 +231,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   k.prolong_smooth(w.la[0], rsrc, w.xl[1].p, w.z.p, w.part_ptr(P_RZ), s);
   const double pb = 2.0 * d0.n * nw + d0.nagg * nw + mat_bytes(d0, !d0.unit, es) + 4.0 * d0.n;
   prof_end(K_PROLONG0, pb);
-  g_rz = grid_for(d0.n, k.rg);
+  g_rz = k.rows_grid(w.la[0], d0.n);
   bytes += pb;
 }
 
@@ -288,7 +296,7 @@ int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner,
     const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es);
     prof_end(K_SPMM, sb);
     bytes += sb;
-    finalize(W, F_ALPHA, grid_for(d0.n, k.rg), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
+    finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
              w.scal.as<double>(), s);
     vcycle(true, first, ra, rb);
     finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
@@ -322,7 +330,7 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   const size_t es = w.fp64 ? 8 : 4;
   std::vector<double> r64(W), b2(W), rel(W, 0.0);
   bool have_x = false;
-  const int gres = grid_for(d0.n, k.rg);
+  const int gres = k.rows_grid(w.la64, d0.n);
   double cur_max = 1.0;
   int step = 0;
   for (;; ++step) {
