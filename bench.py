@@ -29,8 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-DOMINANT = os.environ.get("CFC_PROFILE_KERNEL", "prolong")
-KERNEL_NAMES = {"spmm": "k_spmm_pq", "prolong": "k_prolong_smooth", "restrict": "k_update_restrict"}
+
+
+def kernel_name(idx, depth):
+    """Level-0 kernel kinds timed by the library (see cfc_solve_stats)."""
+    return ["k_spmm_pq", "k_prolong_smooth", "k_update_jacobi" if depth == 1 else "k_update_restrict"][idx]
 
 
 def kernel_source_hash():
@@ -41,10 +44,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, kernel, launches_bytes):
+def load_traffic(workload, kernel):
     """HBM traffic of the dominant kernel from the committed rocprofv3 PMC
     summary, when it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAMES[kernel]}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
@@ -129,6 +132,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--levels", type=int, default=0, help="V-cycle depth (0 = autotuned)")
+    ap.add_argument("--no-full-depth", action="store_true",
+                    help="skip the comparison run with the full multigrid depth")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -137,7 +143,6 @@ def main():
               "(the path would shard right-hand-side columns across GPUs, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("CFC_PROFILE", "1")
-    os.environ.setdefault("CFC_PROFILE_KERNEL", DOMINANT)
     import numpy as np
     import torch
 
@@ -162,24 +167,25 @@ def main():
     info = g.info()
     nodes = synth.query_nodes(eg.n, spec["queries"], seed=1)
     prec = spec.get("precision", 0)
-    kw = dict(tol=spec["tol"], block=spec["block"], precision=prec)
+    kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels)
 
-    def step(seed):
+    def step(seed, **over):
+        kw2 = dict(kw, **over)
         if spec["kind"] == "jl":
-            st = g.jl_sketch(spec["k"], seed=seed, stats=True, **kw)
+            st = g.jl_sketch(spec["k"], seed=seed, stats=True, **kw2)
             g.farness_jl(nodes)
             return st, spec["k"]
         if spec["kind"] == "sampling":
-            _, _, st = g.farness_sampling(nodes, spec["k"], seed=seed, stats=True, **kw)
+            _, _, st = g.farness_sampling(nodes, spec["k"], seed=seed, stats=True, **kw2)
             return st, st["columns"]
-        _, _, st = g.farness_exact(nodes, stats=True, **kw)
+        _, _, st = g.farness_exact(nodes, stats=True, **kw2)
         return st, st["columns"]
 
     for i in range(args.warmup):
         step(1000 + i)
     torch.cuda.synchronize()
-    agg = {"cols": 0, "iters": 0, "refine": 0, "bytes": 0.0, "kms": 0.0, "kbytes": 0.0, "kl": 0,
-           "solve_ms": 0.0, "maxrel": 0.0, "W": 0}
+    agg = {"cols": 0, "iters": 0, "refine": 0, "bytes": 0.0, "kms": [0.0] * 3, "kbytes": [0.0] * 3,
+           "kl": [0] * 3, "solve_ms": 0.0, "maxrel": 0.0, "W": 0}
     t0 = time.perf_counter()
     for i in range(args.steps):
         st, cols = step(1 + i)
@@ -187,26 +193,30 @@ def main():
         agg["iters"] += st["inner_iters"]
         agg["refine"] += st["refine_steps"]
         agg["bytes"] += st["model_bytes"]
-        agg["kms"] += st["spmm_ms"]
-        agg["kbytes"] += st["spmm_bytes"]
-        agg["kl"] += st["spmm_launches"]
+        for j in range(3):
+            agg["kms"][j] += st["kernel_ms"][j]
+            agg["kbytes"][j] += st["kernel_bytes"][j]
+            agg["kl"][j] += st["kernel_launches"][j]
         agg["solve_ms"] += st["solve_ms"]
         agg["maxrel"] = max(agg["maxrel"], st["max_rel_residual"])
         agg["W"] = st["block_width"]
+        agg["depth"] = st["levels_used"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = agg["cols"] / dt
     workload = args.workload
     roof = None
-    if agg["kl"]:
-        per_launch = agg["kbytes"] / agg["kl"]
-        avg_ms = agg["kms"] / agg["kl"]
+    dom = max(range(3), key=lambda j: agg["kms"][j])
+    if agg["kl"][dom]:
+        per_launch = agg["kbytes"][dom] / agg["kl"][dom]
+        avg_ms = agg["kms"][dom] / agg["kl"][dom]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        kname = kernel_name(dom, agg["depth"])
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(workload, DOMINANT, per_launch),
-                "kernel": KERNEL_NAMES[DOMINANT], "avg_launch_us": round(avg_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": per_launch, "launches": agg["kl"]}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(workload, kname),
+                "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": per_launch, "launches": agg["kl"][dom],
+                "share_of_solve_time": round(agg["kms"][dom] / max(agg["solve_ms"], 1e-9), 3)}
     out = {
         "metric": "solved RHS/s at 1e-6 rel. residual", "value": round(value, 2),
         "unit": "solved RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -214,6 +224,7 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64" if prec == 0 else "f64", "data": "synthetic",
         "config": {"workload": workload, "graph": eg.name, "n": eg.n, "m": eg.m,
                    "estimator": spec["kind"], "k": spec.get("k"), "block_width": agg["W"],
+                   "vcycle_depth": agg.get("depth"),
                    "tol": spec["tol"], "query_nodes": spec["queries"], "levels": info["levels"],
                    "operator_complexity": round(info["operator_complexity"], 3)},
         "roofline": roof,
@@ -224,6 +235,17 @@ def main():
                   "whole_path_hbm_frac": round(agg["bytes"] / (dt * 1e9) / HBM_PEAK_GBS, 4),
                   "setup_s": round(setup_s, 3)},
     }
+    if not args.no_full_depth and info["levels"] > 1 and agg["depth"] != info["levels"]:
+        # the same workload through the full multigrid depth, for comparison
+        step(2000, levels=info["levels"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cols = 0
+        for i in range(2):
+            cols += step(3000 + i, levels=info["levels"])[1]
+        torch.cuda.synchronize()
+        out["full_depth_multigrid"] = {"value": round(cols / (time.perf_counter() - t1), 2),
+                                       "unit": "solved RHS/s", "vcycle_depth": info["levels"]}
     if not args.no_fp64_baseline:
         # the plain FP64 one-right-hand-side-at-a-time GPU solve on the same
         # hierarchy: 8 pair right-hand sides

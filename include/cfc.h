@@ -126,6 +126,12 @@ typedef struct {
                             FP64 mode uses tol) */
   int32_t use_graph;     /* 1 = replay a captured HIP graph per PCG iteration */
   int32_t check_every;   /* PCG iterations between host convergence checks (1) */
+  int32_t levels;        /* V-cycle depth: hierarchy levels used by the
+                            preconditioner (1 = Jacobi on the fine level only,
+                            all levels = exact coarsest solve); a truncated
+                            cycle smooths once on its deepest level;
+                            0 = autotuned for the graph */
+  int32_t pad;
 } cfc_solve_params;
 
 typedef struct {
@@ -136,13 +142,20 @@ typedef struct {
   int64_t blocks;         /* RHS blocks processed */
   int32_t block_width;    /* W used */
   int32_t precision;
+  int32_t levels_used;    /* V-cycle depth used */
+  int32_t pad;
   double max_rel_residual;/* largest final ||b - L x|| / ||b|| (FP64) */
   double solve_ms;        /* device time of the solve phase (HIP events) */
   double model_bytes;     /* algorithmic HBM bytes of the solve phase */
-  double spmm_ms;         /* device time in the dominant kernel (HIP events,
-                             only when CFC_PROFILE=1) */
-  double spmm_bytes;      /* algorithmic bytes of that kernel */
-  int64_t spmm_launches;
+  /* Level-0 kernel timing with HIP events on the launch stream (only when
+   * the environment sets CFC_PROFILE=1): index 0 = the CG operator product
+   * (k_spmm_pq), 1 = prolongation + post-smoothing (k_prolong_smooth),
+   * 2 = CG update fused with pre-smoothing and restriction
+   * (k_update_restrict) or, at depth one, with the Jacobi step
+   * (k_update_jacobi). */
+  double kernel_ms[3];
+  double kernel_bytes[3];  /* algorithmic bytes of those launches */
+  int64_t kernel_launches[3];
 } cfc_solve_stats;
 
 /* Level view for inspection (host arrays owned by the graph; valid until

@@ -54,9 +54,9 @@ def jl_sign_word(seed: int, word: int, lo: int, hi: int) -> int:
 
 
 def solve_params(tol=1e-6, precision=PREC_MIXED, block=0, max_refine=20, max_inner=300,
-                 inner_tol=1e-4, use_graph=0, check_every=1) -> _lib.SolveParams:
+                 inner_tol=1e-4, use_graph=0, check_every=1, levels=0) -> _lib.SolveParams:
     return _lib.SolveParams(tol, precision, block, max_refine, max_inner, inner_tol, use_graph,
-                            check_every)
+                            check_every, levels, 0)
 
 
 def setup_params(coarsest_max=512, agg_cap=8, test_vectors=8, relax_sweeps=8, omega=2.0 / 3.0,

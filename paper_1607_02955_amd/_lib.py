@@ -49,18 +49,23 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("precision", C.c_int32), ("block", C.c_int32),
                 ("max_refine", C.c_int32), ("max_inner", C.c_int32), ("inner_tol", C.c_double),
-                ("use_graph", C.c_int32), ("check_every", C.c_int32)]
+                ("use_graph", C.c_int32), ("check_every", C.c_int32), ("levels", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("columns", C.c_int64), ("converged", C.c_int64), ("inner_iters", C.c_int64),
                 ("refine_steps", C.c_int64), ("blocks", C.c_int64), ("block_width", C.c_int32),
-                ("precision", C.c_int32), ("max_rel_residual", C.c_double), ("solve_ms", C.c_double),
-                ("model_bytes", C.c_double), ("spmm_ms", C.c_double), ("spmm_bytes", C.c_double),
-                ("spmm_launches", C.c_int64)]
+                ("precision", C.c_int32), ("levels_used", C.c_int32), ("pad", C.c_int32),
+                ("max_rel_residual", C.c_double), ("solve_ms", C.c_double),
+                ("model_bytes", C.c_double), ("kernel_ms", C.c_double * 3),
+                ("kernel_bytes", C.c_double * 3), ("kernel_launches", C.c_int64 * 3)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        for f in ("kernel_ms", "kernel_bytes", "kernel_launches"):
+            d[f] = list(d[f])
+        return d
 
 
 class LevelView(C.Structure):

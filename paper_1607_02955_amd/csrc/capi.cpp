@@ -230,7 +230,7 @@ int cfc_hierarchy_build(cfc_graph* gg, const cfc_setup_params* p) {
   Graph* g = G(gg);
   std::lock_guard<std::mutex> lk(g->mu);
   build_hierarchy(*g, p ? *p : default_setup());
-  g->tuned_W = 0;
+  g->tuned.clear();
   if (!g->ctx->host_only()) upload_hierarchy(*g);
   return CFC_OK;
   CFC_CATCH

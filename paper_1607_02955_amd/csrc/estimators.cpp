@@ -26,6 +26,8 @@ cfc_solve_params default_solve() {
   p.inner_tol = 1e-4;
   p.use_graph = 0;
   p.check_every = 1;
+  p.levels = 0;
+  p.pad = 0;
   return p;
 }
 
@@ -46,12 +48,18 @@ static void check_params(const cfc_solve_params& p) {
   if (p.max_refine < 0 || p.max_inner < 1) fail(CFC_E_INVALID, "bad iteration limits");
   if (!(p.inner_tol > 0 && p.inner_tol < 1)) fail(CFC_E_INVALID, "inner_tol must be in (0, 1)");
   if (p.block != 0 && !kern_table(p.block, false)) fail(CFC_E_INVALID, "block must be 0, 1, 32, 64, 128, 256 or 512");
+  if (p.levels < 0 || p.levels > CFC_MAX_LEVELS) fail(CFC_E_INVALID, "levels must be in [0, 32]");
 }
 
 // ---------------------------------------------------------------------------
-// autotuner: time a short solve per candidate width, keep the cheapest time
-// per column-iteration; cached in the graph and optionally on disk
-// (CFC_TUNE_CACHE names a text file of "n nnz levels precision W" lines).
+// Autotuner: the block width W and the V-cycle depth that minimise device
+// time per solved column.  Each candidate solves W sample pair right-hand
+// sides for one refinement step (inner tolerance 1e-3, at most 100 PCG
+// iterations) and is scored by solve time / (W * decades of residual
+// reduction), after a warm-up run.  Depth is chosen first at W = 256 (or
+// the fixed W), then W at that depth.  Results are cached in the graph and,
+// when CFC_TUNE_CACHE names a file, on disk as "n nnz levels precision
+// requested-W W depth" lines.
 
 static std::string tune_key(const Graph& g, int prec) {
   std::ostringstream o;
@@ -59,69 +67,123 @@ static std::string tune_key(const Graph& g, int prec) {
   return o.str();
 }
 
-int choose_block(Graph& g, const cfc_solve_params& p0, int64_t ncols) {
-  if (p0.block) return p0.block;
-  const int prec = p0.precision;
-  if (g.tuned_W && (g.tuned_W >> 16) == prec + 1) return g.tuned_W & 0xffff;
+static double tune_score(Graph& g, const cfc_solve_params& p0, int W, int depth) {
+  cfc_solve_params p = p0;
+  p.block = W;
+  p.levels = depth;
+  p.max_refine = 1;
+  p.max_inner = 100;
+  p.check_every = 4;
+  p.inner_tol = 1e-3;
+  p.tol = 1e-300;
+  std::vector<int64_t> s(W), t(W);
+  for (int j = 0; j < W; ++j) {
+    s[j] = (int64_t)((uint64_t(j) * 2654435761ull + 12345) % uint64_t(g.n));
+    t[j] = (int64_t)((uint64_t(j) * 40503ull + 17 + uint64_t(g.n) / 2) % uint64_t(g.n));
+    if (s[j] == t[j]) t[j] = (t[j] + 1) % g.n;
+  }
+  std::vector<double> out(W);
+  double score = 1e300;
+  for (int rep = 0; rep < 2; ++rep) {  // the first run allocates and warms up
+    cfc_solve_stats st{};
+    pair_solves(g, W, s.data(), t.data(), out.data(), p, &st, nullptr);
+    const double rel = std::max(st.max_rel_residual, 1e-12);
+    const double digits = rel < 1 ? -std::log10(rel) : 1e-3;
+    score = st.solve_ms / (W * digits);
+  }
+  return score;
+}
+
+static bool width_fits(const Graph& g, int W, int prec) {
+  double n = 0;
+  for (const auto& l : g.D->lv) n += (double)l.n;
+  const double n0 = (double)g.D->lv[0].n;
+  const double es = prec == CFC_PREC_FP64 ? 8 : 4;
+  const double need = (n0 * (6 * es + 16) + 2 * (n - n0) * es) * W * 1.1;
+  const uint64_t budget = g.ctx->budget;
+  if (budget && g.ctx->in_use + need > (double)budget) return false;
+  size_t freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > 0.7 * (double)freeb) return false;
+  return true;
+}
+
+cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p0, int64_t ncols) {
+  cfc_solve_params p = p0;
+  if (p.block && p.levels) return p;
+  const int prec = p.precision;
+  const int nlev = (int)g.D->lv.size();
+  for (const auto& t : g.tuned)
+    if (t[0] == prec && t[1] == p0.block) {
+      if (!p.block) p.block = t[2];
+      if (!p.levels) p.levels = t[3];
+      return p;
+    }
   const char* cache = std::getenv("CFC_TUNE_CACHE");
-  const std::string key = tune_key(g, prec);
+  const std::string key = tune_key(g, prec) + " " + std::to_string(p0.block);
   if (cache) {
     std::ifstream f(cache);
     std::string line;
     while (std::getline(f, line)) {
-      if (line.rfind(key + " ", 0) == 0) {
-        int W = std::atoi(line.c_str() + key.size() + 1);
-        if (kern_table(W, false)) {
-          g.tuned_W = ((prec + 1) << 16) | W;
-          return W;
-        }
+      if (line.rfind(key + " ", 0) != 0) continue;
+      std::istringstream is(line.substr(key.size() + 1));
+      int W = 0, d = 0;
+      is >> W >> d;
+      if (kern_table(W, false) && d >= 1 && d <= nlev) {
+        g.tuned.push_back({prec, p0.block, W, d});
+        if (!p.block) p.block = W;
+        if (!p.levels) p.levels = d;
+        return p;
       }
     }
   }
-  std::vector<int> cand = prec == CFC_PREC_FP64 ? std::vector<int>{64, 128, 256}
-                                                : std::vector<int>{64, 128, 256, 512};
-  const double n0 = (double)g.n;
-  const double es = prec == CFC_PREC_FP64 ? 8 : 4;
-  double best_t = 1e300;
-  int best = 256;
-  const uint64_t budget = g.ctx->budget;
-  for (int W : cand) {
-    if (ncols > 0 && W > 64 && W / 2 >= ncols) break;  // would leave most columns idle
-    const double need = n0 * W * (6 * es + 16) * 1.6;
-    if (budget && g.ctx->in_use + need > budget) break;
-    size_t freeb = 0, totalb = 0;
-    if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > 0.8 * (double)freeb) break;
-    cfc_solve_params p = p0;
-    p.block = W;
-    p.max_refine = 1;
-    p.max_inner = 4;
-    p.check_every = 1000;
-    p.inner_tol = 1e-12;
-    std::vector<int64_t> s(W), t(W);
-    for (int j = 0; j < W; ++j) {
-      s[j] = (int64_t)((uint64_t(j) * 2654435761ull) % uint64_t(g.n));
-      t[j] = (int64_t)((uint64_t(j) * 40503ull + 17) % uint64_t(g.n));
+  std::vector<int> widths = prec == CFC_PREC_FP64 ? std::vector<int>{64, 128, 256}
+                                                   : std::vector<int>{64, 128, 256, 512};
+  std::vector<int> ok;
+  for (int W : widths) {
+    if (ncols > 0 && W > 64 && W / 2 >= ncols) continue;  // would leave most columns idle
+    if (width_fits(g, W, prec)) ok.push_back(W);
+  }
+  if (ok.empty()) ok.push_back(64);
+  int W0 = p.block;
+  if (!W0) {
+    W0 = ok.front();
+    for (int W : ok)
+      if (W <= 256) W0 = W;
+  }
+  int best_d = p.levels;
+  if (!best_d) {
+    std::vector<int> depths = {1, 2, 3, nlev};
+    std::sort(depths.begin(), depths.end());
+    depths.erase(std::unique(depths.begin(), depths.end()), depths.end());
+    double bs = 1e300;
+    for (int d : depths) {
+      if (d < 1 || d > nlev) continue;
+      const double sc = tune_score(g, p, W0, d);
+      if (sc < bs) { bs = sc; best_d = d; }
     }
-    std::vector<double> out(W);
-    double tm = 1e300;
-    for (int rep = 0; rep < 2; ++rep) {  // first run allocates and warms up
-      cfc_solve_stats st{};
-      pair_solves(g, W, s.data(), t.data(), out.data(), p, &st, nullptr);
-      const double its = std::max<int64_t>(1, st.inner_iters) + 2.0;
-      tm = st.solve_ms / (its * W);
+  }
+  int best_W = p.block;
+  if (!best_W) {
+    double bs = 1e300;
+    for (int W : ok) {
+      const double sc = tune_score(g, p, W, best_d);
+      if (sc < bs) { bs = sc; best_W = W; }
     }
-    if (tm < best_t) { best_t = tm; best = W; }
   }
   // release workspaces of the losing widths
   g.ws.erase(std::remove_if(g.ws.begin(), g.ws.end(),
-                            [&](const std::unique_ptr<Workspace>& w) { return w->W != best; }),
+                            [&](const std::unique_ptr<Workspace>& w) { return w->W != best_W; }),
              g.ws.end());
-  g.tuned_W = ((prec + 1) << 16) | best;
-  if (cache) {
-    std::ofstream f(cache, std::ios::app);
-    f << key << ' ' << best << '\n';
+  if (!p0.levels) {
+    g.tuned.push_back({prec, p0.block, best_W, best_d});
+    if (cache) {
+      std::ofstream f(cache, std::ios::app);
+      f << key << ' ' << best_W << ' ' << best_d << '\n';
+    }
   }
-  return best;
+  p.block = best_W;
+  p.levels = best_d;
+  return p;
 }
 
 // ---------------------------------------------------------------------------
@@ -150,8 +212,7 @@ void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_s
     if (std::fabs(s) > 1e-12 * a + 1e-300 && a > 0)
       fail(CFC_E_INVALID, "B column " + std::to_string(j) + " does not sum to zero");
   }
-  cfc_solve_params p = p0;
-  p.block = choose_block(g, p0, nrhs);
+  cfc_solve_params p = tune_params(g, p0, nrhs);
   Solver S(g, p);
   Workspace& w = *S.ws;
   const int W = w.W;
@@ -200,8 +261,7 @@ void pair_solves(Graph& g, int64_t npairs, const int64_t* s, const int64_t* t, d
   check_params(p0);
   for (int64_t j = 0; j < npairs; ++j)
     if (s[j] < 0 || s[j] >= g.n || t[j] < 0 || t[j] >= g.n) fail(CFC_E_INVALID, "node id out of range");
-  cfc_solve_params p = p0;
-  p.block = choose_block(g, p0, npairs);
+  cfc_solve_params p = tune_params(g, p0, npairs);
   Solver S(g, p);
   Workspace& w = *S.ws;
   const int W = w.W;
@@ -245,8 +305,7 @@ void pair_solves(Graph& g, int64_t npairs, const int64_t* s, const int64_t* t, d
 void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p0, cfc_solve_stats* st) {
   check_params(p0);
   if (k < 1) fail(CFC_E_INVALID, "k must be >= 1");
-  cfc_solve_params p = p0;
-  p.block = choose_block(g, p0, k);
+  cfc_solve_params p = tune_params(g, p0, k);
   g.jl.valid = false;
   const int n0 = g.D->lv[0].n;
   Solver S(g, p);

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <cstdint>
 #include <memory>
@@ -97,7 +98,9 @@ struct Hierarchy {
 // Device copy of one level.
 struct DevLevel {
   int n = 0, nnz = 0, nagg = 0;
+  int light_nnz = 0, nheavy = 0, nseg = 0;  // heavy rows live in their own CSR
   DBuf rowptr, col, w32, w64, deg32, deg64, sdinv32, sdinv64, agg, aggptr;
+  DBuf heavy, hseg, hptr, hcol, hw32, hw64, seg_e;
   bool unit = false;
   float omega32 = 0;
   double omega64 = 0;
@@ -139,7 +142,8 @@ struct Graph {
   std::unique_ptr<DevHierarchy> D;
   std::vector<std::unique_ptr<Workspace>> ws;
   JLSketch jl;
-  int tuned_W = 0;
+  // autotuned (precision, requested W or 0, W, depth)
+  std::vector<std::array<int, 4>> tuned;
   std::mutex mu;
   Graph();
   ~Graph();

@@ -24,6 +24,18 @@ struct LevelArgs {
   double omega = 2.0 / 3.0;
   double mu = 1.5;
   int split = 1;    // row groups sharing each row / aggregate: 1, 4 or 16
+  // Heavy rows (degree above a threshold) keep no edges in the CSR above;
+  // their edges sit in a separate CSR cut into segments that whole
+  // workgroups sum in a pre-pass (partials hpart[segment][W]), and the main
+  // kernels add a heavy row's segment partials in order.
+  int nheavy = 0, nseg = 0;
+  const int* heavy = nullptr;  // [n] heavy index of a row, -1 if light
+  const int* hseg = nullptr;   // [nheavy+1] segment range of each heavy row
+  const int* hptr = nullptr;   // [nheavy+1] edge range of each heavy row
+  const int* hcol = nullptr;   // heavy edges: column
+  const void* hw = nullptr;    // heavy edges: weight (T), nullptr = all ones
+  const int* seg_e = nullptr;  // [nseg+1] edge range of each segment
+  void* hpart = nullptr;       // [nseg][W] partial sums (element type T)
 };
 
 // Right-hand side of the FP64 residual kernel.
@@ -58,6 +70,13 @@ struct KernTable {
   // Prolong + post-smooth: xt = S b + mu xc[agg], x = xt + S (b - L xt); partial b.x if part
   void (*prolong_smooth)(const LevelArgs&, const void* b, const void* xc, void* x,
                          double* part_rz, hipStream_t);
+  // x = S b (Jacobi step from zero) on a level; partial b.x if part
+  void (*jacobi)(const LevelArgs&, const void* b, void* x, double* part, hipStream_t);
+  // Jacobi-PCG update on level 0: r_out = r_in - alpha q, x += alpha p,
+  // z = S r_out; partials |r_out|^2, sum x, r_out.z
+  void (*update_jacobi)(const LevelArgs&, const void* r_in, const void* q, const void* p, void* x,
+                        void* r_out, void* z, const double* scal, int first, double* prr,
+                        double* pcs, double* prz, hipStream_t);
   // Coarsest solve x = Lc^+ b (FP64 arithmetic); Lc^+ is nc_pad x nc_pad.
   void (*coarse)(int nc, int nc_pad, const double* pinv, const void* b, void* x, hipStream_t);
   // Partial dots b.x over n rows (for the single-level case).

@@ -5,7 +5,7 @@
 // columns and workgroup b works on slice b mod NS: the hardware deals
 // workgroups to the 8 XCDs round-robin, so with NS = 8 each XCD touches only
 // its own column slice of every gathered row and its private L2 holds 1/8 of
-// the block.  Inside a slice a "row group" of LPR lanes owns one row at a
+// the block (narrower blocks use fewer, 32-column slices).  Inside a slice a "row group" of LPR lanes owns one row at a
 // time, each lane V consecutive columns (WS = LPR * V), so a neighbour's
 // slice row is one coalesced WS*sizeof(T)-byte read.  The row groups of a
 // workgroup walk a contiguous range of row tiles.
@@ -29,7 +29,9 @@ namespace dev {
 
 // Column slicing and lane shape of a W-wide block.
 template <int W> struct Shape {
-  static constexpr int NS = W >= 32 ? 8 : 1;  // column slices (one per XCD)
+  // column slices: at most one per XCD, each at least 32 columns wide so a
+  // slice row (>= 128 B in FP32) fills whole cache lines
+  static constexpr int NS = W >= 256 ? 8 : (W >= 32 ? W / 32 : 1);
   static constexpr int WS = W / NS;           // columns per slice
   static constexpr int V = WS >= 4 ? 4 : 1;   // columns per lane
   static constexpr int LPR = WS / V;          // lanes per row group
@@ -147,6 +149,74 @@ __device__ __forceinline__ void wg_combine(T* nb, T* lds) {
   __syncthreads();
 }
 
+// nb += the segment partials of heavy row u (fixed order); no-op for a light row.
+template <typename T, int W>
+__device__ __forceinline__ void add_heavy(const LevelArgs& L, int u, T* nb, int c0) {
+  if (!L.heavy) return;
+  const int h = L.heavy[u];
+  if (h < 0) return;
+  constexpr int V = Shape<W>::V;
+  const T* hp = static_cast<const T*>(L.hpart);
+  for (int sgi = L.hseg[h]; sgi < L.hseg[h + 1]; ++sgi) {
+    const Vec<T, V> x = ld<T, V>(hp + (size_t)sgi * W + c0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) nb[i] += x.v[i];
+  }
+}
+
+// Heavy-row pre-pass: one workgroup per (segment, column slice); its row
+// groups split the segment's edges and row group 0 stores the sum
+// hpart[seg] = sum_e w_e f(col_e) with f chosen by KIND.
+enum HeavyKind { HK_SPMM = 0, HK_RESTRICT = 1, HK_RESTRICT_UPD = 2, HK_PROLONG = 3, HK_RES64 = 4 };
+
+template <typename T, int W, int KIND>
+__global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restrict__ a,
+                                                  const T* __restrict__ q, const T* __restrict__ xc,
+                                                  const double* __restrict__ scal) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ T ldc[RG * WS];
+  int slice, sgi, nsg;
+  slice_of_block<W>(slice, sgi, nsg);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  const T* w = static_cast<const T*>(L.hw);
+  const T* sd = static_cast<const T*>(L.sd);
+  const T mu = T(L.mu);
+  T alpha[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) alpha[i] = KIND == HK_RESTRICT_UPD ? T(scal[S_ALPHA * W + c0 + i]) : T(0);
+  for (; sgi < L.nseg; sgi += nsg) {
+    T nb[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) nb[i] = 0;
+    gather_acc<T, W>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
+      Vec<T, V> r = ld<T, V>(a + (size_t)v * W + c0);
+      if constexpr (KIND == HK_RESTRICT || KIND == HK_RESTRICT_UPD) {
+        if constexpr (KIND == HK_RESTRICT_UPD) {
+          const Vec<T, V> qv = ld<T, V>(q + (size_t)v * W + c0);
+#pragma unroll
+          for (int i = 0; i < V; ++i) r.v[i] -= alpha[i] * qv.v[i];
+        }
+        const T f = sd[v];
+#pragma unroll
+        for (int i = 0; i < V; ++i) r.v[i] *= f;
+      } else if constexpr (KIND == HK_PROLONG) {
+        const T f = sd[v];
+        const Vec<T, V> xv = ld<T, V>(xc + (size_t)L.agg[v] * W + c0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) r.v[i] = f * r.v[i] + mu * xv.v[i];
+      }
+      return r;
+    });
+    wg_combine<T, W, RG>(nb, ldc);
+    if (rg == 0) {
+      Vec<T, V> o;
+#pragma unroll
+      for (int i = 0; i < V; ++i) o.v[i] = nb[i];
+      st<T, V>(static_cast<T*>(L.hpart) + (size_t)sgi * W + c0, o);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // PCG step on level 0: q = L z + beta q, p = z + beta p; partial p.q
 template <typename T, int W, int SPLIT>
@@ -182,6 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
                        [&](int v) { return ld<T, V>(z + (size_t)v * W + c0); });
     if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(nb, ldc);
     if (u < L.n && D::leader(rg)) {
+      add_heavy<T, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
       const Vec<T, V> zu = ld<T, V>(z + o);
       const T du = deg[u];
@@ -267,6 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_update_restrict(
         }
 #pragma unroll
         for (int i = 0; i < V; ++i) s[i] += om1 * rn.v[i];
+        if (RESTRICT) add_heavy<T, W>(L, u, s, c0);
       }
       if (RESTRICT)
         gather_acc<T, W>(s, L.col, w, L.rowptr[r0], L.rowptr[r1], D::split(rg), SPLIT, [&](int v) {
@@ -338,6 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
       });
     if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(nb, ldc);
     if (u < L.n && D::leader(rg)) {
+      add_heavy<T, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
       const Vec<T, V> bu = ld<T, V>(b + o);
       const Vec<T, V> cu = ld<T, V>(xc + (size_t)L.agg[u] * W + c0);
@@ -354,6 +427,93 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
     }
   }
   if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+}
+
+// ---------------------------------------------------------------------------
+// Smoother-only "solve" on the deepest level a truncated V-cycle uses:
+// x = S b (one Jacobi step from zero, S = omega D^-1); partial b.x if part.
+template <typename T, int W, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restrict__ b,
+                                                   T* __restrict__ x, double* __restrict__ part) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[DOT ? RG * WS : 1];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  const T* sd = static_cast<const T*>(L.sd);
+  double acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = 0;
+  int tb, te;
+  block_tiles((L.n + RG - 1) / RG, rb, grb, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int u = t * RG + rg;
+    if (u >= L.n) continue;
+    const size_t o = (size_t)u * W + c0;
+    const Vec<T, V> bu = ld<T, V>(b + o);
+    const T su = sd[u];
+    Vec<T, V> xo;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      xo.v[i] = su * bu.v[i];
+      if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
+    }
+    st<T, V>(x + o, xo);
+  }
+  if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+}
+
+// Jacobi-preconditioned CG update on level 0 (a V-cycle of depth one):
+// r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, z = S r_out;
+// partials |r_out|^2, sum x, r_out . z.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* __restrict__ r_in,
+                                                          const T* __restrict__ q, const T* __restrict__ p,
+                                                          T* __restrict__ x, T* __restrict__ r_out,
+                                                          T* __restrict__ z, const double* __restrict__ scal,
+                                                          int first, double* __restrict__ part_rr,
+                                                          double* __restrict__ part_cs,
+                                                          double* __restrict__ part_rz) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[RG * WS];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  const T* sd = static_cast<const T*>(L.sd);
+  T alpha[V];
+  double rr[V], cs[V], rz[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    alpha[i] = T(scal[S_ALPHA * W + c0 + i]);
+    rr[i] = cs[i] = rz[i] = 0;
+  }
+  int tb, te;
+  block_tiles((L.n + RG - 1) / RG, rb, grb, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int u = t * RG + rg;
+    if (u >= L.n) continue;
+    const size_t o = (size_t)u * W + c0;
+    Vec<T, V> rn = ld<T, V>(r_in + o);
+    const Vec<T, V> qu = ld<T, V>(q + o), pu = ld<T, V>(p + o);
+    Vec<T, V> xu, zu;
+    if (!first) xu = ld<T, V>(x + o);
+    const T su = sd[u];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      rn.v[i] -= alpha[i] * qu.v[i];
+      xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
+      zu.v[i] = su * rn.v[i];
+      rr[i] += double(rn.v[i]) * double(rn.v[i]);
+      cs[i] += double(xu.v[i]);
+      rz[i] += double(rn.v[i]) * double(zu.v[i]);
+    }
+    st<T, V>(x + o, xu);
+    st<T, V>(r_out + o, rn);
+    st<T, V>(z + o, zu);
+  }
+  block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
+  block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
+  block_store<W>(rz, lds, part_rz + (size_t)rb * W + slice * WS);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,6 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double
                             [&](int v) { return ld<double, V>(x + (size_t)v * W + c0); });
     if constexpr (SPLIT > 1) wg_combine<double, W, SPLIT>(nb, ldc);
     if (u < L.n && D::leader(rg)) {
+      if (x) add_heavy<double, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
       double a[V];
       if (x) {
@@ -534,10 +695,15 @@ __global__ __launch_bounds__(kBlock) void k_jl_rhs(LevelArgs L, const int* __res
     double a[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) a[i] = 0;
-    for (int e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e) {
-      const uint64_t gv = uint64_t(iperm[L.col[e]]);
+    const int hh = L.heavy ? L.heavy[u] : -1;
+    const int e0 = hh >= 0 ? L.hptr[hh] : L.rowptr[u];
+    const int e1 = hh >= 0 ? L.hptr[hh + 1] : L.rowptr[u + 1];
+    const int* cl = hh >= 0 ? L.hcol : L.col;
+    const double* wl = hh >= 0 ? static_cast<const double*>(L.hw) : w;
+    for (int e = e0; e < e1; ++e) {
+      const uint64_t gv = uint64_t(iperm[cl[e]]);
       const uint64_t lo = gu < gv ? gu : gv, hi = gu < gv ? gv : gu;
-      const double sw = w ? sqrt(w[e]) : 1.0;
+      const double sw = wl ? sqrt(wl[e]) : 1.0;
       const double sg = gu < gv ? sw : -sw;
       const uint64_t h = jl_word(seed, word, lo, hi);
 #pragma unroll
@@ -636,8 +802,18 @@ struct Launch {
       hipLaunchKernelGGL((K<__VA_ARGS__, 1>), dim3(g_ * NS), dim3(kBlock), 0, s, ARGS);        \
   } while (0)
 
+  template <int KIND>
+  static void heavy(const LevelArgs& L, const void* a, const void* q, const void* xc,
+                    const double* scal, hipStream_t s) {
+    if (!L.nseg) return;
+    const int g = std::min(L.nseg, 4 * kMaxGrid);
+    hipLaunchKernelGGL((k_heavy<T, W, KIND>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)a,
+                       (const T*)q, (const T*)xc, scal);
+  }
+
   static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, const double* scal,
                       int first, double* part, hipStream_t s) {
+    heavy<HK_SPMM>(L, z, nullptr, nullptr, scal, s);
 #define ARGS L, (const T*)z, (T*)p, (T*)q, scal, first, part
     CFC_LAUNCH(k_spmm_pq, L.n, T, W);
 #undef ARGS
@@ -646,6 +822,8 @@ struct Launch {
                               void* x, void* r_out, void* bc, const double* scal, int first,
                               int do_update, double* prr, double* pcs, hipStream_t s) {
     const bool R = L.nagg > 0;
+    if (R && do_update) heavy<HK_RESTRICT_UPD>(L, r_in, q, nullptr, scal, s);
+    else if (R) heavy<HK_RESTRICT>(L, r_in, nullptr, nullptr, scal, s);
 #define ARGS L, (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal, first, prr, pcs
     if (do_update && R)
       CFC_LAUNCH(k_update_restrict, L.nagg, T, W, true, true);
@@ -656,6 +834,7 @@ struct Launch {
 #undef ARGS
   }
   static void restrict_(const LevelArgs& L, const void* b, void* bc, hipStream_t s) {
+    heavy<HK_RESTRICT>(L, b, nullptr, nullptr, nullptr, s);
 #define ARGS L, (const T*)b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)bc, \
              (const double*)nullptr, 0, (double*)nullptr, (double*)nullptr
     CFC_LAUNCH(k_update_restrict, L.nagg, T, W, false, true);
@@ -663,12 +842,31 @@ struct Launch {
   }
   static void prolong_smooth(const LevelArgs& L, const void* b, const void* xc, void* x,
                              double* part, hipStream_t s) {
+    heavy<HK_PROLONG>(L, b, nullptr, xc, nullptr, s);
 #define ARGS L, (const T*)b, (const T*)xc, (T*)x, part
     if (part)
       CFC_LAUNCH(k_prolong_smooth, L.n, T, W, true);
     else
       CFC_LAUNCH(k_prolong_smooth, L.n, T, W, false);
 #undef ARGS
+  }
+  static void jacobi(const LevelArgs& L, const void* b, void* x, double* part, hipStream_t s) {
+    const int g = grid_units(L.n, RG);
+    if (!g) return;
+    if (part)
+      hipLaunchKernelGGL((k_jacobi<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)b,
+                         (T*)x, part);
+    else
+      hipLaunchKernelGGL((k_jacobi<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)b,
+                         (T*)x, part);
+  }
+  static void update_jacobi(const LevelArgs& L, const void* r_in, const void* q, const void* p,
+                            void* x, void* r_out, void* z, const double* scal, int first,
+                            double* prr, double* pcs, double* prz, hipStream_t s) {
+    const int g = grid_units(L.n, RG);
+    if (!g) return;
+    hipLaunchKernelGGL((k_update_jacobi<T, W>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r_in,
+                       (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)z, scal, first, prr, pcs, prz);
   }
   static void coarse(int nc, int ncp, const double* A, const void* b, void* x, hipStream_t s) {
 #ifndef CFC_COARSE_NO_MFMA
@@ -691,6 +889,10 @@ struct Launch {
   }
   static void residual64(const LevelArgs& L, const double* x64, RhsArgs rhs, void* r_out,
                          double* part, hipStream_t s) {
+    if (x64 && L.nseg)
+      hipLaunchKernelGGL((k_heavy<double, W, HK_RES64>), dim3(std::min(L.nseg, 4 * kMaxGrid) * NS),
+                         dim3(kBlock), 0, s, L, x64, (const double*)nullptr, (const double*)nullptr,
+                         (const double*)nullptr);
 #define ARGS L, x64, rhs, (T*)r_out, part
     CFC_LAUNCH(k_residual64, L.n, T, W);
 #undef ARGS
@@ -738,6 +940,8 @@ struct Launch {
     t.restrict_ = &restrict_;
     t.prolong_smooth = &prolong_smooth;
     t.coarse = &coarse;
+    t.jacobi = &jacobi;
+    t.update_jacobi = &update_jacobi;
     t.dot = &dot;
     t.residual64 = &residual64;
     t.xupdate64 = &xupdate64;

@@ -54,6 +54,7 @@ struct GraphWorker {
   ServerImpl* srv = nullptr;
   Graph* g = nullptr;
   int gid = 0;
+  int depth = 0;                    // V-cycle depth (autotuned at registration)
   hipStream_t stream = nullptr;
   std::thread th;
   std::deque<ColTask> pending;      // guarded by srv->mu
@@ -107,7 +108,8 @@ static uint64_t workspace_bytes(const Graph& g, int W) {
 void GraphWorker::run() {
   ServerImpl& S = *srv;
   (void)hipSetDevice(S.ctx->device);
-  const cfc_solve_params p = serve_params(S.opts);
+  cfc_solve_params p = serve_params(S.opts);
+  p.levels = depth;
   const int W = p.block;
   std::unique_ptr<Solver> sol;
   std::vector<ColTask> slot(W);
@@ -329,6 +331,7 @@ int cfc_server_add_graph(cfc_server* s, cfc_graph* gh, int32_t* gid) {
     auto w = std::make_unique<GraphWorker>();
     w->srv = s;
     w->g = g;
+    w->depth = tune_params(*g, serve_params(s->opts), s->opts.slots).levels;
     CFC_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
     GraphWorker* wp = w.get();
     {

@@ -41,6 +41,11 @@ void upload_hierarchy(Graph& g) {
   const int L = (int)H.lv.size();
   D->lv.resize(L);
   hipStream_t s = c->stream;
+  static const int heavy_deg = [] {
+    const char* e = std::getenv("CFC_HEAVY_DEG");
+    return e ? std::max(16, std::atoi(e)) : 512;
+  }();
+  const int seg_len = heavy_deg;
   for (int l = 0; l < L; ++l) {
     const HostLevel& h = H.lv[l];
     DevLevel& d = D->lv[l];
@@ -48,23 +53,60 @@ void upload_hierarchy(Graph& g) {
     d.nnz = (int)h.nnz();
     d.nagg = h.aggptr.empty() ? 0 : (int)h.aggptr.size() - 1;
     d.unit = (l == 0) && g.unit;
-    upload(c, d.rowptr, h.rowptr, s);
-    upload(c, d.col, h.col, s);
-    std::vector<float> w32(h.w.size()), deg32(h.n), sd32(h.n);
+    // light CSR (heavy rows keep no edges) + heavy CSR cut into segments
+    std::vector<int32_t> lptr(h.n + 1, 0), lcol, hid(h.n, -1), hptr(1, 0), hcol, hseg(1, 0), seg_e(1, 0);
+    std::vector<double> lw, hw;
+    lcol.reserve(h.col.size());
+    lw.reserve(h.w.size());
+    for (int64_t r = 0; r < h.n; ++r) {
+      const int32_t e0 = h.rowptr[r], e1 = h.rowptr[r + 1];
+      if (e1 - e0 > heavy_deg) {
+        hid[r] = d.nheavy++;
+        for (int32_t e = e0; e < e1; ++e) {
+          hcol.push_back(h.col[e]);
+          hw.push_back(h.w[e]);
+          if ((int)(hcol.size() - hptr.back()) % seg_len == 0) seg_e.push_back((int32_t)hcol.size());
+        }
+        if (seg_e.back() != (int32_t)hcol.size()) seg_e.push_back((int32_t)hcol.size());
+        hptr.push_back((int32_t)hcol.size());
+        hseg.push_back((int32_t)seg_e.size() - 1);
+      } else {
+        for (int32_t e = e0; e < e1; ++e) {
+          lcol.push_back(h.col[e]);
+          lw.push_back(h.w[e]);
+        }
+      }
+      lptr[r + 1] = (int32_t)lcol.size();
+    }
+    d.light_nnz = (int)lcol.size();
+    d.nseg = (int)seg_e.size() - 1;
+    upload(c, d.rowptr, lptr, s);
+    upload(c, d.col, lcol, s);
+    std::vector<float> w32(lw.size()), deg32(h.n), sd32(h.n), hw32(hw.size());
     std::vector<double> sd64(h.n);
-    for (size_t i = 0; i < h.w.size(); ++i) w32[i] = (float)h.w[i];
+    for (size_t k = 0; k < lw.size(); ++k) w32[k] = (float)lw[k];
+    for (size_t k = 0; k < hw.size(); ++k) hw32[k] = (float)hw[k];
     for (int64_t r = 0; r < h.n; ++r) {
       // FP32 diagonal = FP32 sum of the FP32 off-diagonals, so that the FP32
       // operator keeps its row sums (L 1 = 0) as closely as FP32 allows.
       float sacc = 0.f;
-      for (int32_t e = h.rowptr[r]; e < h.rowptr[r + 1]; ++e) sacc += w32[e];
+      for (int32_t e = h.rowptr[r]; e < h.rowptr[r + 1]; ++e) sacc += (float)h.w[e];
       deg32[r] = sacc;
       sd32[r] = sacc > 0 ? (float)(H.omega / (double)sacc) : 0.f;
       sd64[r] = h.deg[r] > 0 ? H.omega / h.deg[r] : 0.0;
     }
     if (!d.unit) {
       upload(c, d.w32, w32, s);
-      upload(c, d.w64, h.w, s);
+      upload(c, d.w64, lw, s);
+      upload(c, d.hw32, hw32, s);
+      upload(c, d.hw64, hw, s);
+    }
+    if (d.nheavy) {
+      upload(c, d.heavy, hid, s);
+      upload(c, d.hseg, hseg, s);
+      upload(c, d.hptr, hptr, s);
+      upload(c, d.hcol, hcol, s);
+      upload(c, d.seg_e, seg_e, s);
     }
     upload(c, d.deg32, deg32, s);
     upload(c, d.deg64, h.deg, s);
@@ -75,8 +117,9 @@ void upload_hierarchy(Graph& g) {
       upload(c, d.aggptr, h.aggptr, s);
     }
     d.omega64 = H.omega;
-    D->bytes += d.rowptr.bytes + d.col.bytes + d.w32.bytes + d.w64.bytes + d.deg32.bytes +
-                d.deg64.bytes + d.sdinv32.bytes + d.sdinv64.bytes + d.agg.bytes + d.aggptr.bytes;
+    for (const DBuf* b : {&d.rowptr, &d.col, &d.w32, &d.w64, &d.deg32, &d.deg64, &d.sdinv32, &d.sdinv64,
+                          &d.agg, &d.aggptr, &d.heavy, &d.hseg, &d.hptr, &d.hcol, &d.hw32, &d.hw64, &d.seg_e})
+      D->bytes += b->bytes;
   }
   // coarsest pseudoinverse, zero-padded to a multiple of 16
   const int nc = (int)H.lv[L - 1].n;
@@ -118,8 +161,18 @@ static LevelArgs level_args(const Graph& g, int l, bool fp64) {
     const char* e = std::getenv("CFC_SPLIT_EDGES");
     return e ? std::atof(e) : 8.0;
   }();
-  const double avg = d.n > 0 ? (double)d.nnz / d.n : 0.0;
+  const double avg = d.n > 0 ? (double)d.light_nnz / d.n : 0.0;
   a.split = avg >= 16 * per_group ? 16 : (avg >= 4 * per_group ? 4 : 1);
+  a.nheavy = d.nheavy;
+  a.nseg = d.nseg;
+  if (d.nheavy) {
+    a.heavy = d.heavy.as<int>();
+    a.hseg = d.hseg.as<int>();
+    a.hptr = d.hptr.as<int>();
+    a.hcol = d.hcol.as<int>();
+    a.hw = d.unit ? nullptr : (fp64 ? (const void*)d.hw64.p : (const void*)d.hw32.p);
+    a.seg_e = d.seg_e.as<int>();
+  }
   return a;
 }
 
@@ -142,6 +195,15 @@ Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s) {
   w.la.resize(L);
   for (int l = 0; l < L; ++l) w.la[l] = level_args(g, l, fp64);
   w.la64 = level_args(g, 0, true);
+  // segment partials of heavy rows, one region per level (FP64-sized so the
+  // FP64 residual can share level 0's region)
+  w.hpart.resize(L);
+  for (int l = 0; l < L; ++l)
+    if (g.D->lv[l].nseg) {
+      w.hpart[l].alloc(c, (size_t)g.D->lv[l].nseg * W * 8);
+      w.la[l].hpart = w.hpart[l].p;
+      if (l == 0) w.la64.hpart = w.hpart[0].p;
+    }
   const size_t es = fp64 ? 8 : 4;
   const size_t n0 = (size_t)g.D->lv[0].n;
   const size_t blk = n0 * W * es;
@@ -184,12 +246,30 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   Workspace& w = *ws;
   const KernTable& k = *w.kt;
   hipStream_t s = stream;
-  const int L = w.nlev;
+  const int L = nuse;                 // levels this cycle visits
+  const bool exact = nuse == w.nlev;  // deepest visited level is the true coarsest
   const size_t es = w.fp64 ? 8 : 4;
   const double nw = (double)w.W * es;
   const DevLevel& d0 = g->D->lv[0];
   const void* rsrc = update ? r_out : r_in;
-  if (L == 1) {
+  if (L == 1 && !exact) {
+    // depth one: Jacobi-preconditioned CG, z = S r
+    if (update) {
+      prof_begin(K_RESTRICT0);
+      k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.z.p, w.scal.as<double>(), first_x,
+                      w.part_ptr(P_RR), w.part_ptr(P_CS), w.part_ptr(P_RZ), s);
+      const double ub = d0.n * nw * (first_x ? 6 : 7) + 2.0 * es * d0.n;
+      prof_end(K_RESTRICT0, ub);
+      bytes += ub;
+      g_rr = g_cs = grid_for(d0.n, k.rg);
+    } else {
+      k.jacobi(w.la[0], r_in, w.z.p, w.part_ptr(P_RZ), s);
+      bytes += d0.n * nw * 2 + es * d0.n;
+    }
+    g_rz = grid_for(d0.n, k.rg);
+    return;
+  }
+  if (L == 1) {  // single-level hierarchy: the preconditioner is L^+ itself
     if (update) {
       LevelArgs a = w.la[0];
       a.nagg = 0;
@@ -219,9 +299,15 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     k.restrict_(w.la[l], w.b[l].p, w.b[l + 1].p, s);
     bytes += d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * (d.nagg + 1);
   }
-  const int nc = g->D->nc;
-  k.coarse(nc, (nc + 15) / 16 * 16, g->D->cpinv.as<double>(), w.b[L - 1].p, w.xl[L - 1].p, s);
-  bytes += 2.0 * nc * nw + 8.0 * nc * nc;
+  if (exact) {
+    const int nc = g->D->nc;
+    k.coarse(nc, (nc + 15) / 16 * 16, g->D->cpinv.as<double>(), w.b[L - 1].p, w.xl[L - 1].p, s);
+    bytes += 2.0 * nc * nw + 8.0 * nc * nc;
+  } else {
+    const DevLevel& d = g->D->lv[L - 1];
+    k.jacobi(w.la[L - 1], w.b[L - 1].p, w.xl[L - 1].p, nullptr, s);
+    bytes += 2.0 * d.n * nw + es * d.n;
+  }
   for (int l = L - 2; l >= 1; --l) {
     const DevLevel& d = g->D->lv[l];
     k.prolong_smooth(w.la[l], w.b[l].p, w.xl[l + 1].p, w.xl[l].p, nullptr, s);
@@ -236,29 +322,32 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
 }
 
 void Solver::prof_begin(int which) {
-  if (!profile || which != prof_kernel) return;
-  hipEvent_t a;
-  CFC_HIP(hipEventCreate(&a));
-  CFC_HIP(hipEventRecord(a, stream));
-  prof_ev.push_back(a);
+  if (!profile) return;
+  ProfEv e{which, 0.0, nullptr, nullptr};
+  CFC_HIP(hipEventCreate(&e.a));
+  CFC_HIP(hipEventRecord(e.a, stream));
+  prof_ev.push_back(e);
 }
 void Solver::prof_end(int which, double b) {
-  if (!profile || which != prof_kernel) return;
-  hipEvent_t e;
-  CFC_HIP(hipEventCreate(&e));
-  CFC_HIP(hipEventRecord(e, stream));
-  prof_ev.push_back(e);
-  prof_bytes += b;
-  prof_launches++;
+  if (!profile || prof_ev.empty() || prof_ev.back().kind != which || prof_ev.back().b) return;
+  ProfEv& e = prof_ev.back();
+  CFC_HIP(hipEventCreate(&e.b));
+  CFC_HIP(hipEventRecord(e.b, stream));
+  e.bytes = b;
 }
 void Solver::prof_collect() {
-  for (size_t i = 0; i + 1 < prof_ev.size(); i += 2) {
-    float ms = 0;
-    CFC_HIP(hipEventSynchronize(prof_ev[i + 1]));
-    CFC_HIP(hipEventElapsedTime(&ms, prof_ev[i], prof_ev[i + 1]));
-    prof_ms += ms;
+  for (auto& e : prof_ev) {
+    if (e.b) {
+      float ms = 0;
+      CFC_HIP(hipEventSynchronize(e.b));
+      CFC_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+      prof_ms[e.kind] += ms;
+      prof_bytes[e.kind] += e.bytes;
+      prof_launches[e.kind]++;
+      (void)hipEventDestroy(e.b);
+    }
+    (void)hipEventDestroy(e.a);
   }
-  for (auto e : prof_ev) (void)hipEventDestroy(e);
   prof_ev.clear();
 }
 
@@ -388,18 +477,18 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so) : g(&gr), p
   debug = dbg && dbg[0] == '1';
   const char* pe = std::getenv("CFC_PROFILE");
   profile = pe && pe[0] == '1';
-  const char* pk = std::getenv("CFC_PROFILE_KERNEL");
-  prof_kernel = K_SPMM;
-  if (pk && std::strcmp(pk, "prolong") == 0) prof_kernel = K_PROLONG0;
-  if (pk && std::strcmp(pk, "restrict") == 0) prof_kernel = K_RESTRICT0;
   ws = &get_workspace(*g, p.block, p.precision == CFC_PREC_FP64, stream);
+  nuse = (p.levels >= 1 && p.levels <= ws->nlev) ? p.levels : ws->nlev;
   CFC_HIP(hipEventCreate(&ev0));
   CFC_HIP(hipEventCreate(&ev1));
   CFC_HIP(hipEventRecord(ev0, stream));
 }
 
 Solver::~Solver() {
-  for (auto e : prof_ev) (void)hipEventDestroy(e);
+  for (auto& e : prof_ev) {
+    (void)hipEventDestroy(e.a);
+    if (e.b) (void)hipEventDestroy(e.b);
+  }
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
 }
@@ -418,12 +507,15 @@ void Solver::finish(cfc_solve_stats* st) {
   st->blocks += blocks;
   st->block_width = ws->W;
   st->precision = params.precision;
+  st->levels_used = nuse;
   st->max_rel_residual = std::max(st->max_rel_residual, max_rel);
   st->solve_ms += ms;
   st->model_bytes += bytes;
-  st->spmm_ms += prof_ms;
-  st->spmm_bytes += prof_bytes;
-  st->spmm_launches += prof_launches;
+  for (int k = 0; k < 3; ++k) {
+    st->kernel_ms[k] += prof_ms[k];
+    st->kernel_bytes[k] += prof_bytes[k];
+    st->kernel_launches[k] += prof_launches[k];
+  }
 }
 
 }  // namespace cfc

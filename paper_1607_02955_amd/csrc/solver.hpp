@@ -20,6 +20,7 @@ struct Workspace {
   LevelArgs la64;             // level 0 in FP64
   DBuf x, ra, rb, p, q, z;    // level 0, inner element type
   std::vector<DBuf> b, xl;    // levels >= 1: right-hand side and iterate
+  std::vector<DBuf> hpart;    // per level: heavy-row segment partials
   DBuf x64;                   // FP64 solution block
   DBuf rhs;                   // FP64 dense right-hand sides (on demand)
   DBuf pairs;                 // int32 ps[W], pt[W], segment bounds
@@ -40,16 +41,21 @@ struct Solver {
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int g_rz = 0, g_rr = 0, g_cs = 0;
+  int nuse = 1;  // V-cycle depth
   // statistics
   int64_t columns = 0, converged = 0, inner_iters = 0, refine_steps = 0, blocks = 0;
   double max_rel = 0, bytes = 0;
   // kernel timing with HIP events on the launch stream (CFC_PROFILE=1)
   bool profile = false;
   bool debug = false;
-  int prof_kernel = K_SPMM;
-  std::vector<hipEvent_t> prof_ev;
-  double prof_ms = 0, prof_bytes = 0;
-  int64_t prof_launches = 0;
+  struct ProfEv {
+    int kind;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfEv> prof_ev;
+  double prof_ms[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0};
+  int64_t prof_launches[3] = {0, 0, 0};
 
   Solver(Graph& g, const cfc_solve_params& p, hipStream_t stream_override = nullptr);
   ~Solver();
@@ -65,8 +71,9 @@ struct Solver {
 };
 
 cfc_solve_params default_solve();
-// Pick W for the graph (autotuner; cached in the graph).
-int choose_block(Graph& g, const cfc_solve_params& p, int64_t ncols);
+// Fill in block width and V-cycle depth left at 0 (autotuner; cached in
+// the graph and optionally on disk).
+cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p, int64_t ncols);
 
 // Estimators (estimators.cpp)
 void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_solve_params& p,

@@ -73,6 +73,65 @@ def test_block_widths_weighted_random(ctx, W):
         assert r[0] == 0.0
 
 
+def hub_graph(seed=21):
+    """Random weighted graph plus three hubs adjacent to most nodes (rows far
+    above the heavy-row degree threshold at several levels)."""
+    base = synth.random_connected(3000, 9000, seed=seed)
+    rng = np.random.default_rng(seed)
+    u = [base.u]
+    v = [base.v]
+    for h, cnt in [(7, 2500), (1500, 1800), (2999, 700)]:
+        nb = rng.choice(np.setdiff1d(np.arange(3000), [h]), cnt, replace=False)
+        u.append(np.full(cnt, h))
+        v.append(nb)
+    u = np.concatenate(u)
+    v = np.concatenate(v)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    key = np.unique(lo * 3000 + hi)
+    w = rng.uniform(1.0, 4.0, key.shape[0])
+    return synth.EdgeList(3000, key // 3000, key % 3000, w, "hubs")
+
+
+@pytest.mark.parametrize("W,depth", [(64, 1), (256, 2), (512, 0), (32, 3)])
+def test_heavy_rows(ctx, W, depth):
+    eg = hub_graph()
+    say("heavy rows", W, depth, eg.n, eg.m)
+    g = load(ctx, eg, coarsest_max=64)
+    Lp, Rm = dense_R(eg)
+    rng = np.random.default_rng(W)
+    s = rng.integers(0, eg.n, W + 5)
+    t = rng.integers(0, eg.n, W + 5)
+    s[:3] = [7, 1500, 2999]
+    for prec, tol, rt in [(0, 1e-8, 1e-7), (1, 1e-10, 1e-9)]:
+        r = g.resistance(s, t, block=W, precision=prec, tol=tol, levels=depth, max_inner=2000)
+        np.testing.assert_allclose(r, Rm[s, t], rtol=rt, atol=1e-12)
+    g.jl_sketch(40, seed=3, tol=1e-9, block=W, levels=depth, max_inner=2000)
+    nodes = np.array([7, 1500, 2999, 11])
+    far, _ = g.farness_jl(nodes)
+    of, _, _ = E.projection(None, eg, nodes, 40, 3, solver="dense", Lp=Lp)
+    np.testing.assert_allclose(far, of, rtol=1e-6)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 0])
+def test_vcycle_depths(ctx, depth):
+    """Every V-cycle depth (1 = Jacobi-PCG, truncated cycles, full with the
+    exact coarsest solve, 0 = autotuned) solves to the same resistances."""
+    eg = synth.road_grid(60, seed=3)
+    say("depth", depth, eg.n, eg.m)
+    g = load(ctx, eg, coarsest_max=64)
+    nlev = g.info()["levels"]
+    assert nlev >= 4
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(depth)
+    s = rng.integers(0, eg.n, 70)
+    t = rng.integers(0, eg.n, 70)
+    for prec, tol, rt in [(0, 1e-8, 1e-7), (1, 1e-10, 1e-9)]:
+        r, st = g.resistance(s, t, block=64, precision=prec, tol=tol, levels=depth, stats=True,
+                             max_inner=3000)
+        assert st["levels_used"] == (depth if depth else st["levels_used"]) and st["levels_used"] >= 1
+        np.testing.assert_allclose(r, Rm[s, t], rtol=rt, atol=1e-12)
+
+
 @pytest.mark.parametrize("maker,name", [
     (lambda: synth.path_graph(300), "path"),
     (lambda: synth.cycle_graph(301), "cycle"),
