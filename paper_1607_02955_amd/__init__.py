@@ -12,7 +12,9 @@ provides the HIP stream and, through its caching allocator, device memory.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -24,6 +26,21 @@ from ._lib import (COL_DIVERGED, COL_NOT_CONVERGED, COL_OK, COL_SKIPPED, LCC_ONL
 __all__ = ["Context", "Graph", "Server", "CfcError", "sampling_pivots", "jl_sign_word", "version",
            "LCC_ONLY", "REJECT_PARALLEL", "PREC_MIXED", "PREC_FP64", "QUERY_JL", "QUERY_SAMPLING",
            "COL_OK", "COL_NOT_CONVERGED", "COL_DIVERGED", "COL_SKIPPED", "solve_params"]
+
+
+# Live handles, closed in dependency order (servers, graphs, contexts) at
+# interpreter exit while the host runtime and torch are still intact.
+_live = {"server": weakref.WeakSet(), "graph": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_all():
+    for kind in ("server", "graph", "ctx"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 def _i64(a):
@@ -111,6 +128,7 @@ class Context:
         check(lib().cfc_ctx_create(C.byref(opts), C.byref(h)))
         self.handle = h
         self.device = device
+        _live["ctx"].add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -142,6 +160,7 @@ class Graph:
         check(lib().cfc_graph_load(ctx.handle, n, u.shape[0], _p(u, C.c_int64), _p(v, C.c_int64),
                                    wp, flags, C.byref(h)))
         self.handle = h
+        _live["graph"].add(self)
         inf = self.info()
         self.n = inf["n"]
         self.m = inf["m"]
@@ -288,6 +307,7 @@ class Server:
         check(lib().cfc_server_create(ctx.handle, C.byref(o), C.byref(h)))
         self.handle = h
         self.graphs = []
+        _live["server"].add(self)
 
     def add_graph(self, g: Graph) -> int:
         gid = C.c_int32()
@@ -310,7 +330,7 @@ class Server:
             return None
         check(rc)
         if r.status != 0:
-            raise CfcError(r.status, "query failed")
+            raise CfcError(r.status, "query failed")  # e.g. CFC_E_NOMEM, CFC_E_NOT_CONVERGED
         return far[:r.nnodes].copy(), clo[:r.nnodes].copy(), r.latency_ms
 
     def poll(self, ticket):

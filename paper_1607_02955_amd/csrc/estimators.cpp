@@ -349,7 +349,8 @@ void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p0, c
   if (!g.jl.valid) fail(CFC_E_NOT_CONVERGED, "projection solves missed the tolerance");
 }
 
-void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* clo) {
+void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* clo, Ctx* mem,
+                hipStream_t stream) {
   if (!g.jl.valid) fail(CFC_E_STATE, "no projection sketch (call cfc_jl_sketch)");
   if (q < 0 || (q > 0 && (!nodes || !far))) fail(CFC_E_INVALID, "bad arguments");
   std::vector<int> idx(q);
@@ -358,12 +359,12 @@ void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* 
     idx[i] = g.H.perm[nodes[i]];
   }
   if (q == 0) return;
-  Ctx* c = g.ctx;
+  Ctx* c = mem ? mem : g.ctx;
   DBuf di, dn, dt;
   di.alloc(c, q * sizeof(int));
   dn.alloc(c, q * sizeof(double));
   dt.alloc(c, q * sizeof(double));
-  hipStream_t s = c->stream;
+  hipStream_t s = stream ? stream : g.ctx->stream;
   CFC_HIP(hipMemcpyAsync(di.p, idx.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
   gather((int)q, g.jl.N_dev.as<double>(), di.as<int>(), dn.as<double>(), s);
   gather((int)q, g.jl.T_dev.as<double>(), di.as<int>(), dt.as<double>(), s);

@@ -66,6 +66,10 @@ struct GraphWorker {
 
 struct ServerImpl {
   Ctx* ctx = nullptr;
+  // Worker threads allocate slot workspaces through this context: plain
+  // hipMalloc on the same device, never the caller's allocator callbacks
+  // (which may call back into a host runtime from a foreign thread).
+  Ctx wctx;
   cfc_server_opts opts{};
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_admit;
@@ -133,9 +137,11 @@ void GraphWorker::run() {
         q->far.resize(q->nodes.size());
         q->clo.resize(q->nodes.size());
         Graph& G = *g;
-        if (!G.jl.valid) fail(CFC_E_STATE, "graph has no projection sketch");
+        if (S.opts.jl_k <= 0 || !G.jl.valid || G.jl.k != S.opts.jl_k || G.jl.seed != S.opts.seed)
+          fail(CFC_E_STATE, "the server keeps no projection sketch for this graph");
         // jl_farness uses the context stream; serialise on it
-        jl_farness(G, (int64_t)q->nodes.size(), q->nodes.data(), q->far.data(), q->clo.data());
+        jl_farness(G, (int64_t)q->nodes.size(), q->nodes.data(), q->far.data(), q->clo.data(),
+                   &S.wctx, stream);
       } catch (const Error& e) {
         rc = e.code;
       } catch (...) {
@@ -173,7 +179,7 @@ void GraphWorker::run() {
           S.admitted_bytes += need;
           reserved = need;
         }
-        sol = std::make_unique<Solver>(*g, p, stream);
+        sol = std::make_unique<Solver>(*g, p, stream, &S.wctx);
         zero_fill(sol->ws->x64.p, sol->ws->x64.bytes, stream);
       }
       Workspace& w = *sol->ws;
@@ -275,10 +281,9 @@ void GraphWorker::run() {
       pending.clear();
     }
   }
-  if (sol) {
-    (void)hipStreamSynchronize(stream);
-    sol.reset();
-  }
+  (void)hipStreamSynchronize(stream);
+  sol.reset();
+  g->ws.clear();  // these were allocated through the server's context
 }
 
 }  // namespace cfc
@@ -298,6 +303,8 @@ int cfc_server_create(cfc_ctx* ctx, const cfc_server_opts* o, cfc_server** out) 
     if (c->host_only()) fail(CFC_E_STATE, "server needs a device context");
     auto s = std::make_unique<cfc_server>();
     s->ctx = c;
+    s->wctx.device = c->device;
+    s->wctx.stream = c->stream;
     cfc_server_opts d{256, 4096, 256, 200, 1, 1e-6, 0};
     s->opts = o ? *o : d;
     if (!kern_table(s->opts.slots, false) || s->opts.slots < 32)
@@ -332,6 +339,10 @@ int cfc_server_add_graph(cfc_server* s, cfc_graph* gh, int32_t* gid) {
     w->srv = s;
     w->g = g;
     w->depth = tune_params(*g, serve_params(s->opts), s->opts.slots).levels;
+    // workspaces the graph holds from direct calls (and the tuning runs) were
+    // allocated with the caller's allocator: release them on this thread
+    CFC_HIP(hipStreamSynchronize(s->ctx->stream));
+    g->ws.clear();
     CFC_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
     GraphWorker* wp = w.get();
     {

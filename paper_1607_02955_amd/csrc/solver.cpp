@@ -180,10 +180,10 @@ Workspace::~Workspace() {
   if (pinned) (void)hipHostFree(pinned);
 }
 
-Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s) {
+Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem) {
   for (auto& w : g.ws)
     if (w->W == W && w->fp64 == fp64) return *w;
-  Ctx* c = g.ctx;
+  Ctx* c = mem ? mem : g.ctx;
   auto ws = std::make_unique<Workspace>();
   Workspace& w = *ws;
   w.W = W;
@@ -470,14 +470,14 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   blocks++;
 }
 
-Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so) : g(&gr), params(p) {
+Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) : g(&gr), params(p) {
   if (!g->D) fail(CFC_E_STATE, "hierarchy not built on a device (call cfc_hierarchy_build)");
   stream = so ? so : g->ctx->stream;
   const char* dbg = std::getenv("CFC_DEBUG");
   debug = dbg && dbg[0] == '1';
   const char* pe = std::getenv("CFC_PROFILE");
   profile = pe && pe[0] == '1';
-  ws = &get_workspace(*g, p.block, p.precision == CFC_PREC_FP64, stream);
+  ws = &get_workspace(*g, p.block, p.precision == CFC_PREC_FP64, stream, mem);
   nuse = (p.levels >= 1 && p.levels <= ws->nlev) ? p.levels : ws->nlev;
   CFC_HIP(hipEventCreate(&ev0));
   CFC_HIP(hipEventCreate(&ev1));

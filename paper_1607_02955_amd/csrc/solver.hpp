@@ -32,7 +32,7 @@ struct Workspace {
   double* part_ptr(int which) const;
 };
 
-Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s);
+Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem = nullptr);
 
 struct Solver {
   Graph* g;
@@ -57,7 +57,10 @@ struct Solver {
   double prof_ms[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0};
   int64_t prof_launches[3] = {0, 0, 0};
 
-  Solver(Graph& g, const cfc_solve_params& p, hipStream_t stream_override = nullptr);
+  // stream_override: launch stream (default: the context's); mem: context
+  // whose allocator backs new workspaces (default: the graph's)
+  Solver(Graph& g, const cfc_solve_params& p, hipStream_t stream_override = nullptr,
+         Ctx* mem = nullptr);
   ~Solver();
   void vcycle(bool update, bool first_x, const void* r_in, void* r_out);
   int pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
@@ -82,6 +85,7 @@ void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_s
 void pair_solves(Graph& g, int64_t npairs, const int64_t* s, const int64_t* t, double* out,
                  const cfc_solve_params& p, cfc_solve_stats* st, int32_t* col_status);
 void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p, cfc_solve_stats* st);
-void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* clo);
+void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* clo,
+                Ctx* mem = nullptr, hipStream_t stream = nullptr);
 
 }  // namespace cfc
