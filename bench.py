@@ -75,6 +75,99 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def serve_mix(args):
+    """Serving: 8 resident graphs (BA n=1e4/1e5/1e6, R-MAT scale 16/18/20,
+    grids 512^2 and 1536^2, unit weights), each with a resident projection
+    sketch (k=256).  A seeded Poisson stream of farness queries (graph
+    uniform, node subset of U{1..32} nodes, half projection / half Sampling
+    with 200 pivots) arrives at half the measured saturation rate; the server
+    batches Sampling columns into 256 slots per graph.  Reports queries/s and
+    p50/p99 latency (arrival to result on the host)."""
+    import numpy as np
+    import torch
+
+    import paper_1607_02955_amd as cfc
+    import synth
+
+    specs = [("ba1e4", synth.barabasi_albert, (10000, 4)), ("ba1e5", synth.barabasi_albert, (100000, 4)),
+             ("ba1e6", synth.barabasi_albert, (1000000, 4)),
+             ("rmat16", lambda *a: synth.rmat(*a, weights=None), (16, 16)),
+             ("rmat18", lambda *a: synth.rmat(*a, weights=None), (18, 16)),
+             ("rmat20u", lambda *a: synth.rmat(*a, weights=None), (20, 16)),
+             ("grid512", synth.grid, (512,)), ("grid1536", synth.grid, (1536,))]
+    ctx = cfc.Context(0)
+    t0 = time.perf_counter()
+    egs, gs = [], []
+    for name, fn, a in specs:
+        eg = synth.cached(name, fn, *a)
+        egs.append(eg)
+        gs.append(cfc.Graph.from_edgelist(ctx, eg).build_hierarchy())
+        print(f"# loaded {name} n={eg.n} m={eg.m} ({time.perf_counter() - t0:.0f}s)", file=sys.stderr, flush=True)
+    srv = cfc.Server(ctx, slots=256, jl_k=256, sampling_k=200, seed=1, tol=1e-6)
+    ids = []
+    for (name, _, _), g in zip(specs, gs):
+        ids.append(srv.add_graph(g))
+        print(f"# registered {name} ({time.perf_counter() - t0:.0f}s)", file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t0
+    rng = np.random.default_rng(7)
+
+    def draw():
+        gi = int(rng.integers(0, len(egs)))
+        nn = int(rng.integers(1, 33))
+        nodes = rng.choice(egs[gi].n, nn, replace=False)
+        kind = cfc.QUERY_JL if rng.random() < 0.5 else cfc.QUERY_SAMPLING
+        return ids[gi], kind, nodes
+
+    # saturation: a burst of queries submitted at once
+    burst = [draw() for _ in range(args.burst)]
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    ts = [srv.submit(*q) for q in burst]
+    for t in ts:
+        srv.wait(t)
+    sat = len(ts) / (time.perf_counter() - tb)
+    print(f"# saturation ~{sat:.1f} queries/s", file=sys.stderr, flush=True)
+    srv.close()
+    # fresh server for the timed Poisson stream (clean latency statistics)
+    srv = cfc.Server(ctx, slots=256, jl_k=256, sampling_k=200, seed=1, tol=1e-6)
+    ids[:] = [srv.add_graph(g) for g in gs]
+    rate = args.rate_frac * sat
+    gaps = rng.exponential(1.0 / rate, size=100000)
+    tickets = []
+    start = time.perf_counter()
+    t_next = start
+    i = 0
+    while time.perf_counter() - start < args.duration:
+        now = time.perf_counter()
+        if now < t_next:
+            time.sleep(min(t_next - now, 0.01))
+            continue
+        tickets.append(srv.submit(*draw()))
+        t_next += gaps[i]
+        i += 1
+    lat = []
+    for t in tickets:
+        r = srv.wait(t)
+        lat.append(r[2])
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    lat = np.array(lat)
+    out = {"metric": "farness queries/s (serving) + p50/p99 latency", "value": round(len(tickets) / wall, 3),
+           "unit": "queries/s", "n_gpus": 1, "steps": len(tickets), "warmup": args.burst,
+           "ms_per_step": round(1e3 * wall / max(1, len(tickets)), 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "serve_mix", "graphs": [s[0] for s in specs], "slots": 256, "jl_k": 256,
+                      "sampling_k": 200, "tol": 1e-6, "arrival_rate_qps": round(rate, 3),
+                      "saturation_qps": round(sat, 3), "duration_s": args.duration},
+           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                          "p99": round(float(np.percentile(lat, 99)), 3),
+                          "mean": round(float(lat.mean()), 3), "server_p50": round(st["p50_ms"], 3),
+                          "server_p99": round(st["p99_ms"], 3)},
+           "setup_s": round(setup_s, 1)}
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(eg, spec, budget_s=20.0):
     """The oracle (plain FP64 Jacobi-preconditioned CG, numpy/scipy) on a
     bounded sample of the same right-hand sides, single-threaded."""
@@ -133,6 +226,11 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--levels", type=int, default=0, help="V-cycle depth (0 = autotuned)")
+    ap.add_argument("--use-graph", type=int, default=-1,
+                    help="replay PCG iterations from a HIP graph (1/0; default: on for n < 100000)")
+    ap.add_argument("--duration", type=float, default=30.0, help="serve_mix: seconds of arrivals")
+    ap.add_argument("--rate-frac", type=float, default=0.5, help="serve_mix: arrival rate / saturation")
+    ap.add_argument("--burst", type=int, default=64, help="serve_mix: queries in the saturation burst")
     ap.add_argument("--no-full-depth", action="store_true",
                     help="skip the comparison run with the full multigrid depth")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -155,6 +253,10 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copies": 5}))
         return
 
+    if args.workload == "serve_mix":
+        serve_mix(args)
+        return
+
     import paper_1607_02955_amd as cfc
     import synth
 
@@ -167,7 +269,9 @@ def main():
     info = g.info()
     nodes = synth.query_nodes(eg.n, spec["queries"], seed=1)
     prec = spec.get("precision", 0)
-    kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels)
+    use_graph = args.use_graph if args.use_graph >= 0 else int(eg.n < 100000)
+    kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels,
+              use_graph=use_graph)
 
     def step(seed, **over):
         kw2 = dict(kw, **over)
@@ -224,7 +328,7 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64" if prec == 0 else "f64", "data": "synthetic",
         "config": {"workload": workload, "graph": eg.name, "n": eg.n, "m": eg.m,
                    "estimator": spec["kind"], "k": spec.get("k"), "block_width": agg["W"],
-                   "vcycle_depth": agg.get("depth"),
+                   "vcycle_depth": agg.get("depth"), "hip_graph": bool(use_graph),
                    "tol": spec["tol"], "query_nodes": spec["queries"], "levels": info["levels"],
                    "operator_complexity": round(info["operator_complexity"], 3)},
         "roofline": roof,

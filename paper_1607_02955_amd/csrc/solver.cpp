@@ -360,50 +360,84 @@ void Solver::read_scal(int which, double* out) {
   std::memcpy(out, w.pinned, w.W * sizeof(double));
 }
 
-// Preconditioned CG on L d = r0 (r0 in ws.ra); result d in ws.x.  Returns
-// the iteration count.
-int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every) {
+// One PCG iteration on level 0 (operator product, step length, update fused
+// into the first V-cycle kernel, V-cycle, direction scalars).
+void Solver::iteration(bool first, void* r_in, void* r_out) {
   Workspace& w = *ws;
   const KernTable& k = *w.kt;
-  hipStream_t s = stream;
   const DevLevel& d0 = g->D->lv[0];
   const size_t es = w.fp64 ? 8 : 4;
   const double nw = (double)w.W * es;
   const int W = w.W;
+  prof_begin(K_SPMM);
+  k.spmm_pq(w.la[0], w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first, w.part_ptr(P_PQ), stream);
+  const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es);
+  prof_end(K_SPMM, sb);
+  bytes += sb;
+  finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
+           w.scal.as<double>(), stream);
+  vcycle(true, first, r_in, r_out);
+  finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
+           w.scal.as<double>(), stream);
+}
+
+void Solver::capture_pair() {
+  Workspace& w = *ws;
+  const bool prof = profile;
+  profile = false;  // no event records inside the captured graph
+  const double b0 = bytes;
+  CFC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  iteration(false, w.rb.p, w.ra.p);
+  iteration(false, w.ra.p, w.rb.p);
+  CFC_HIP(hipStreamEndCapture(stream, &graph));
+  CFC_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  pair_bytes = bytes - b0;
+  bytes = b0;
+  profile = prof;
+}
+
+// Preconditioned CG on L d = r0 (r0 in ws.ra); result d in ws.x.  Returns
+// the iteration count.  After the first iteration the residual alternates
+// between ws.rb and ws.ra; with use_graph the later iterations replay a
+// captured pair of iterations.
+int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every) {
+  Workspace& w = *ws;
+  const int W = w.W;
   vcycle(false, false, w.ra.p, nullptr);
-  finalize(W, F_RZINIT, g_rz, w.part_ptr(P_RZ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s);
+  finalize(W, F_RZINIT, g_rz, w.part_ptr(P_RZ), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
   std::vector<double> rr(W);
   const double tol2 = inner_tol * inner_tol;
-  int it = 0;
-  void* ra = w.ra.p;
-  void* rb = w.rb.p;
+  auto converged = [&]() {
+    read_scal(S_RR, rr.data());
+    for (int j = 0; j < W; ++j) {
+      if (!(rr0[j] > 0)) continue;
+      if (!std::isfinite(rr[j])) continue;  // reported by the outer residual
+      if (rr[j] > tol2 * rr0[j]) return false;
+    }
+    return true;
+  };
+  int it = 1;
+  iteration(true, w.ra.p, w.rb.p);
+  if (max_inner == 1 || (1 % check_every == 0 && converged())) return it;
+  if (params.use_graph) {
+    if (!gexec) capture_pair();
+    while (it < max_inner) {
+      CFC_HIP(hipGraphLaunch(gexec, stream));
+      it += 2;
+      bytes += pair_bytes;
+      graph_replays++;
+      if ((it / 2) % std::max(1, check_every / 2) == 0 && converged()) break;
+    }
+    return it;
+  }
+  void* ra = w.rb.p;  // current residual
+  void* rb = w.ra.p;
   while (it < max_inner) {
     ++it;
-    const bool first = it == 1;
-    prof_begin(K_SPMM);
-    k.spmm_pq(w.la[0], w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first, w.part_ptr(P_PQ), s);
-    const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es);
-    prof_end(K_SPMM, sb);
-    bytes += sb;
-    finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
-             w.scal.as<double>(), s);
-    vcycle(true, first, ra, rb);
-    finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
-             w.scal.as<double>(), s);
+    iteration(false, ra, rb);
     std::swap(ra, rb);
-    if (it % check_every == 0 || it == max_inner) {
-      read_scal(S_RR, rr.data());
-      bool done = true;
-      for (int j = 0; j < W; ++j) {
-        if (!(rr0[j] > 0)) continue;
-        if (!std::isfinite(rr[j])) continue;  // reported by the outer residual
-        if (rr[j] > tol2 * rr0[j]) { done = false; break; }
-      }
-      if (done) break;
-    }
+    if ((it % check_every == 0 || it == max_inner) && converged()) break;
   }
-  // keep the latest residual in ws.ra for callers that look at it
-  if (ra != w.ra.p) std::swap(w.ra.p, w.rb.p);
   return it;
 }
 
@@ -485,6 +519,8 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
 }
 
 Solver::~Solver() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
   for (auto& e : prof_ev) {
     (void)hipEventDestroy(e.a);
     if (e.b) (void)hipEventDestroy(e.b);

@@ -221,6 +221,24 @@ def test_projection_matches_oracle_same_seed(ctx):
     np.testing.assert_allclose(clo, oc, rtol=1e-6)
 
 
+@pytest.mark.parametrize("W,depth", [(64, 0), (256, 1), (32, 2)])
+def test_graph_replay_matches_eager(ctx, W, depth):
+    """PCG iterations replayed from a captured HIP graph give the same
+    resistances as eager launches (and as the oracle)."""
+    eg = synth.road_grid(40, seed=8)
+    g = load(ctx, eg, coarsest_max=64)
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(W)
+    s = rng.integers(0, eg.n, 2 * W + 3)
+    t = rng.integers(0, eg.n, 2 * W + 3)
+    for prec, tol in [(0, 1e-8), (1, 1e-10)]:
+        kw = dict(block=W, precision=prec, tol=tol, levels=depth, max_inner=3000)
+        r_e = g.resistance(s, t, **kw)
+        r_g = g.resistance(s, t, use_graph=1, **kw)
+        np.testing.assert_allclose(r_g, r_e, rtol=10 * tol)
+        np.testing.assert_allclose(r_g, Rm[s, t], rtol=10 * tol, atol=1e-12)
+
+
 def test_edge_cases(ctx):
     import paper_1607_02955_amd as cfc
     g1 = cfc.Graph(ctx, 1, [], [])
