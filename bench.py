@@ -226,6 +226,7 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--levels", type=int, default=0, help="V-cycle depth (0 = autotuned)")
+    ap.add_argument("--block", type=int, default=-1, help="block width W (default: the workload's)")
     ap.add_argument("--use-graph", type=int, default=-1,
                     help="replay PCG iterations from a HIP graph (1/0; default: on for n < 100000)")
     ap.add_argument("--duration", type=float, default=30.0, help="serve_mix: seconds of arrivals")
@@ -270,6 +271,8 @@ def main():
     nodes = synth.query_nodes(eg.n, spec["queries"], seed=1)
     prec = spec.get("precision", 0)
     use_graph = args.use_graph if args.use_graph >= 0 else int(eg.n < 100000)
+    if args.block >= 0:
+        spec["block"] = args.block
     kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels,
               use_graph=use_graph)
 

@@ -242,12 +242,17 @@ void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_s
     CFC_HIP(hipStreamSynchronize(S.stream));
     for (int j = 0; j < nc; ++j) {
       double* col = Xh + (c0 + j) * n;
-      double m = 0;
+      // mean-zero projection of the returned copy; compensated (Neumaier)
+      // summation keeps the mean accurate to FP64 rounding for large n
+      double sum = 0, comp = 0;
       for (int64_t i = 0; i < n; ++i) {
-        col[i] = xo[(size_t)perm[i] * W + j];
-        m += col[i];
+        const double v = xo[(size_t)perm[i] * W + j];
+        col[i] = v;
+        const double t = sum + v;
+        comp += std::fabs(sum) >= std::fabs(v) ? (sum - t) + v : (v - t) + sum;
+        sum = t;
       }
-      m /= double(n);  // exact FP64 projection of the returned copy
+      const double m = (sum + comp) / double(n);
       for (int64_t i = 0; i < n; ++i) col[i] -= m;
     }
   }

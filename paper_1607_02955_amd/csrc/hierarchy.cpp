@@ -14,13 +14,15 @@
 //     Galerkin operator P^T L P, which is again a graph Laplacian: the quotient
 //     graph with W_IJ = sum of w_uv over u in I, v in J;
 //   * a nested renumbering that makes every aggregate a contiguous row range
-//     on every level (restriction and prolongation then need no atomics and
-//     neighbouring rows stay close in memory);
+//     on every level (restriction and prolongation then need no atomics),
+//     ordered along a Cuthill-McKee sweep of the fine graph so that
+//     neighbouring rows stay close in memory;
 //   * the coarsest level's dense pseudoinverse L_c^+ = Pi G Pi, with G the
 //     inverse of L_c grounded at node 0 (Sec. 4, last paragraph) padded with
 //     a zero row and column, and Pi = I - 11^T / n_c.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <numeric>
 
@@ -258,6 +260,57 @@ std::vector<double> laplacian_pinv(const BLevel& L) {
   return out;
 }
 
+// Cuthill-McKee sweep: breadth-first from a pseudo-peripheral node (the end
+// of a few repeated BFS passes), neighbours visited in ascending degree.
+// Returns the visit position of every node (every component is swept).
+std::vector<int64_t> bfs_keys(const BLevel& L) {
+  const int64_t n = L.n;
+  std::vector<int64_t> key(n, -1), q;
+  q.reserve(n);
+  auto deg = [&](int64_t u) { return L.rowptr[u + 1] - L.rowptr[u]; };
+  auto bfs = [&](int64_t root, std::vector<int64_t>& dist) {
+    dist.assign(n, -1);
+    std::vector<int64_t> qq{root};
+    dist[root] = 0;
+    int64_t last = root;
+    for (size_t h = 0; h < qq.size(); ++h) {
+      const int64_t u = qq[h];
+      last = u;
+      for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e)
+        if (dist[L.col[e]] < 0) {
+          dist[L.col[e]] = dist[u] + 1;
+          qq.push_back(L.col[e]);
+        }
+    }
+    return last;
+  };
+  int64_t next = 0;
+  std::vector<int64_t> dist, nb;
+  for (int64_t start = 0; start < n; ++start) {
+    if (key[start] >= 0) continue;
+    int64_t root = start;
+    for (int it = 0; it < 3; ++it) root = bfs(root, dist);  // pseudo-peripheral
+    const size_t q0 = q.size();
+    q.push_back(root);
+    key[root] = next++;
+    for (size_t h = q0; h < q.size(); ++h) {
+      const int64_t u = q[h];
+      nb.clear();
+      for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e)
+        if (key[L.col[e]] < 0) nb.push_back(L.col[e]);
+      std::sort(nb.begin(), nb.end(), [&](int64_t a, int64_t b) {
+        return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+      });
+      for (int64_t v : nb)
+        if (key[v] < 0) {
+          key[v] = next++;
+          q.push_back(v);
+        }
+    }
+  }
+  return key;
+}
+
 }  // namespace
 
 void build_hierarchy(Graph& g, const cfc_setup_params& p) {
@@ -286,10 +339,26 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   }
   if (B.back().n > 4096) fail(CFC_E_INTERNAL, "coarsening stalled above 4096 nodes");
   const int L = (int)B.size();
-  // nested renumbering, coarsest first
+  // Locality keys: level-0 nodes get their position in a Cuthill-McKee
+  // (breadth-first, ascending degree) sweep from a pseudo-peripheral node; a
+  // coarse node gets the smallest key of its aggregate.
+  std::vector<std::vector<int64_t>> key(L);
+  key[0] = bfs_keys(B[0]);
+  for (int l = 0; l + 1 < L; ++l) {
+    key[l + 1].assign(B[l + 1].n, INT64_MAX);
+    for (int64_t u = 0; u < B[l].n; ++u) {
+      int64_t& k = key[l + 1][B[l].agg[u]];
+      k = std::min(k, key[l][u]);
+    }
+  }
+  // nested renumbering, coarsest first: coarse nodes and the members of each
+  // aggregate in key order, so every aggregate is a contiguous row range and
+  // the numbering follows the sweep on every level
   std::vector<std::vector<int32_t>> order(L), newid(L);
   order[L - 1].resize(B[L - 1].n);
   std::iota(order[L - 1].begin(), order[L - 1].end(), 0);
+  std::stable_sort(order[L - 1].begin(), order[L - 1].end(),
+                   [&](int32_t a, int32_t b) { return key[L - 1][a] < key[L - 1][b]; });
   for (int l = L - 2; l >= 0; --l) {
     const BLevel& F = B[l];
     std::vector<int32_t> start(F.nagg + 1, 0), mem(F.n);
@@ -297,6 +366,9 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
     for (int64_t i = 0; i < F.nagg; ++i) start[i + 1] += start[i];
     std::vector<int32_t> pos(start.begin(), start.end() - 1);
     for (int64_t u = 0; u < F.n; ++u) mem[pos[F.agg[u]]++] = (int32_t)u;
+    for (int64_t I = 0; I < F.nagg; ++I)
+      std::stable_sort(mem.begin() + start[I], mem.begin() + start[I + 1],
+                       [&](int32_t a, int32_t b) { return key[l][a] < key[l][b]; });
     order[l].reserve(F.n);
     for (int32_t I : order[l + 1])
       for (int32_t k = start[I]; k < start[I + 1]; ++k) order[l].push_back(mem[k]);

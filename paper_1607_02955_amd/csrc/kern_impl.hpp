@@ -38,13 +38,21 @@ template <int W> struct Shape {
   static constexpr int RG = kBlock / LPR;     // row groups per workgroup
 };
 
-// Slice of this workgroup and its index among the workgroups of that slice.
+// Slice of this workgroup and its index rb among the grb workgroups of that
+// slice.  Workgroup b runs on XCD b mod 8; the 8/NS XCDs that share a slice
+// each take a contiguous part of the row range (rb blocks in order), so a
+// row's neighbours are most often in the same XCD's L2.
 template <int W>
 __device__ __forceinline__ void slice_of_block(int& slice, int& rb, int& grb) {
   constexpr int NS = Shape<W>::NS;
-  slice = blockIdx.x % NS;
-  rb = blockIdx.x / NS;
+  constexpr int XPS = 8 / NS;  // XCDs per slice
+  const int b = blockIdx.x;
+  slice = b % NS;
   grb = gridDim.x / NS;
+  if ((gridDim.x & 7) == 0 && grb % XPS == 0)
+    rb = ((b & 7) / NS) * (grb / XPS) + (b >> 3);
+  else
+    rb = b / NS;
 }
 
 template <typename T, int V>
@@ -59,6 +67,40 @@ __device__ __forceinline__ Vec<T, V> ld(const T* p) {
 template <typename T, int V>
 __device__ __forceinline__ void st(T* p, const Vec<T, V>& x) {
   *reinterpret_cast<Vec<T, V>*>(p) = x;
+}
+
+// Streaming (non-temporal) row access for values read or written once per
+// kernel: they should not displace the rows that neighbours gather again.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ld_nt(const T* p) {
+  Vec<T, V> r;
+  if constexpr ((sizeof(T) * V) % 16 == 0) {
+    constexpr int C = sizeof(T) * V / 16;
+    const u32x4* q = reinterpret_cast<const u32x4*>(p);
+    u32x4* o = reinterpret_cast<u32x4*>(&r);
+#pragma unroll
+    for (int c = 0; c < C; ++c) o[c] = __builtin_nontemporal_load(q + c);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = __builtin_nontemporal_load(p + i);
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void st_nt(T* p, const Vec<T, V>& x) {
+  if constexpr ((sizeof(T) * V) % 16 == 0) {
+    constexpr int C = sizeof(T) * V / 16;
+    u32x4* q = reinterpret_cast<u32x4*>(p);
+    const u32x4* i = reinterpret_cast<const u32x4*>(&x);
+#pragma unroll
+    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(i[c], q + c);
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) __builtin_nontemporal_store(x.v[k], p + k);
+  }
 }
 
 // Contiguous range of row tiles for row-block rb of G row-blocks.
@@ -262,14 +304,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
 #pragma unroll
         for (int i = 0; i < V; ++i) qn.v[i] = du * zu.v[i] - nb[i];
       } else {
-        const Vec<T, V> po = ld<T, V>(p + o), qo = ld<T, V>(q + o);
+        const Vec<T, V> po = ld_nt<T, V>(p + o), qo = ld_nt<T, V>(q + o);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
           pn.v[i] = zu.v[i] + beta[i] * po.v[i];
           qn.v[i] = (du * zu.v[i] - nb[i]) + beta[i] * qo.v[i];
         }
       }
-      st<T, V>(p + o, pn);
+      st_nt<T, V>(p + o, pn);
       st<T, V>(q + o, qn);
 #pragma unroll
       for (int i = 0; i < V; ++i) acc[i] += double(pn.v[i]) * double(qn.v[i]);
@@ -323,9 +365,9 @@ __global__ __launch_bounds__(kBlock) void k_update_restrict(
         const size_t o = (size_t)u * W + c0;
         Vec<T, V> rn = ld<T, V>(r_in + o);
         if (UPDATE) {
-          const Vec<T, V> qu = ld<T, V>(q + o), pu = ld<T, V>(p + o);
+          const Vec<T, V> qu = ld<T, V>(q + o), pu = ld_nt<T, V>(p + o);
           Vec<T, V> xu;
-          if (!first) xu = ld<T, V>(x + o);
+          if (!first) xu = ld_nt<T, V>(x + o);
 #pragma unroll
           for (int i = 0; i < V; ++i) {
             rn.v[i] -= alpha[i] * qu.v[i];
@@ -333,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_update_restrict(
             rr[i] += double(rn.v[i]) * double(rn.v[i]);
             cs[i] += double(xu.v[i]);
           }
-          st<T, V>(x + o, xu);
+          st_nt<T, V>(x + o, xu);
           st<T, V>(r_out + o, rn);
         }
 #pragma unroll
@@ -423,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
         xo.v[i] = xt + sdu * (bu.v[i] - lx);
         if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
       }
-      st<T, V>(x + o, xo);
+      st_nt<T, V>(x + o, xo);
     }
   }
   if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
@@ -493,10 +535,10 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     const int u = t * RG + rg;
     if (u >= L.n) continue;
     const size_t o = (size_t)u * W + c0;
-    Vec<T, V> rn = ld<T, V>(r_in + o);
-    const Vec<T, V> qu = ld<T, V>(q + o), pu = ld<T, V>(p + o);
+    Vec<T, V> rn = ld_nt<T, V>(r_in + o);
+    const Vec<T, V> qu = ld_nt<T, V>(q + o), pu = ld_nt<T, V>(p + o);
     Vec<T, V> xu, zu;
-    if (!first) xu = ld<T, V>(x + o);
+    if (!first) xu = ld_nt<T, V>(x + o);
     const T su = sd[u];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
@@ -507,8 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
       cs[i] += double(xu.v[i]);
       rz[i] += double(rn.v[i]) * double(zu.v[i]);
     }
-    st<T, V>(x + o, xu);
-    st<T, V>(r_out + o, rn);
+    st_nt<T, V>(x + o, xu);
+    st_nt<T, V>(r_out + o, rn);
     st<T, V>(z + o, zu);
   }
   block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
@@ -634,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double
       }
       double bv[V];
       if (rhs.kind == 0) {
-        const Vec<double, V> bb = ld<double, V>(rhs.dense + o);
+        const Vec<double, V> bb = ld_nt<double, V>(rhs.dense + o);
 #pragma unroll
         for (int i = 0; i < V; ++i) bv[i] = bb.v[i];
       } else {
@@ -648,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double
         ro.v[i] = TO(r);
         acc[i] += r * r;
       }
-      st<TO, V>(r_out + o, ro);
+      st_nt<TO, V>(r_out + o, ro);
     }
   }
   block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
