@@ -110,7 +110,7 @@ typedef struct {
   int32_t agg_cap;       /* maximum aggregate size (8) */
   int32_t test_vectors;  /* relaxed vectors that define affinities (8) */
   int32_t relax_sweeps;  /* relaxation sweeps per test vector (8) */
-  double omega;          /* Jacobi smoothing weight (2/3) */
+  double omega;          /* Jacobi smoothing weight (0.8) */
   double mu;             /* coarse-correction scale, 0 < mu < 2 (1.5) */
   uint64_t seed;         /* test-vector seed (1) */
 } cfc_setup_params;

@@ -37,7 +37,7 @@ cfc_setup_params default_setup() {
   p.agg_cap = 8;
   p.test_vectors = 8;
   p.relax_sweeps = 8;
-  p.omega = 2.0 / 3.0;
+  p.omega = 0.8;
   p.mu = 1.5;
   p.seed = 1;
   return p;

@@ -91,7 +91,7 @@ struct Hierarchy {
   std::vector<int32_t> perm;   // graph node -> level-0 row
   std::vector<int32_t> iperm;  // level-0 row -> graph node
   std::vector<double> cpinv;   // coarsest dense pseudoinverse (row-major)
-  double omega = 2.0 / 3.0, mu = 1.5;
+  double omega = 0.8, mu = 1.5;
   double setup_ms = 0;
 };
 
