@@ -191,8 +191,9 @@ def cpu_baseline(eg, spec, budget_s=20.0):
             t0 = time.perf_counter()
             done = 0
             while time.perf_counter() - t0 < budget_s and done < Y.shape[1]:
-                R.cg(L, Y[:, done:done + cols], tol=spec["tol"])
-                done += cols
+                c = min(cols, Y.shape[1] - done)
+                R.cg(L, Y[:, done:done + c], tol=spec["tol"])
+                done += c
                 cols = min(cols * 2, 16)
             dt = time.perf_counter() - t0
             return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",

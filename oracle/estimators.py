@@ -55,6 +55,32 @@ def sampling(L, g, nodes, k, seed, solver="cg", tol=1e-12, Lp=None):
     return np.array(far), np.array(clo), piv_all, d_all
 
 
+def sampling_shared(L, g, nodes, k, seed, solver="cg", tol=1e-12, Lp=None):
+    """Sampling with one pivot set S for all query nodes (Sec. 5.1 read
+    literally: a single uniform sample of k nodes, drawn by
+    ``rng.shared_pivots``).  The estimate is the same (n/k) sum_S d_ER(v, s)
+    as in :func:`sampling`, each d_ER by its own solve of L p = e_v - e_s.
+
+    Returns (farness_est, closeness_est, S)."""
+    n = g.n
+    S = _rng.shared_pivots(seed, n, k)
+    kk = len(S)
+    far = []
+    clo = []
+    for v in np.atleast_1d(nodes):
+        v = int(v)
+        others = np.array([s for s in S if s != v], np.int64)
+        if others.size == 0:
+            tot = 0.0
+        elif solver == "dense":
+            tot = float(_res.resistance_from_inverse(Lp, np.full(others.shape, v), others).sum())
+        else:
+            tot = float(_res.resistance_cg(L, np.full(others.shape, v), others, tol).sum())
+        far.append(n / kk * tot)
+        clo.append((kk / n) * (n - 1) / tot if tot > 0 else np.inf)
+    return np.array(far), np.array(clo), np.array(S, np.int64)
+
+
 def projection_rhs(g, k, seed, Q=None):
     """Y^T (n x k): column i is (Q W^(1/2) B)_i, row i of Y (Algorithm 1's
     multiplication step).  ``Q`` overrides the random matrix (k x m), e.g. the

@@ -27,6 +27,8 @@ C2 = 0x94D049BB133111EB
 
 TAG_JL = 0x4A4C
 TAG_SAMPLE = 0x5350
+TAG_SHARED = 0x5348
+TAG_PAIRS = 0x4346
 
 
 def splitmix_out(state: int) -> int:
@@ -72,12 +74,17 @@ def lemire_bounded(words, bound: int) -> int:
     return m >> 64
 
 
-def sample_stream(seed: int, node: int):
-    """64-bit words H(seed, TAG_SAMPLE, node, c) for c = 0, 1, 2, ..."""
+def stream(seed: int, tag: int, a: int):
+    """64-bit words H(seed, tag, a, c) for c = 0, 1, 2, ..."""
     c = 0
     while True:
-        yield hash4(seed, TAG_SAMPLE, node, c)
+        yield hash4(seed, tag, a, c)
         c += 1
+
+
+def sample_stream(seed: int, node: int):
+    """64-bit words H(seed, TAG_SAMPLE, node, c) for c = 0, 1, 2, ..."""
+    return stream(seed, TAG_SAMPLE, node)
 
 
 def floyd_subset(n: int, k: int, words) -> list:
@@ -94,6 +101,29 @@ def pivots(seed: int, node: int, n: int, k: int) -> list:
     """The pivot set S of Sec. 5.1 for query node ``node``: a uniform k-subset
     of all of V (the node itself may be drawn, as in the proof of Prop. 1)."""
     return floyd_subset(n, k, sample_stream(seed, node))
+
+
+def shared_pivots(seed: int, n: int, k: int) -> list:
+    """One pivot set for every query node (the literal reading of Sec. 5.1,
+    where a single sample of k nodes is drawn): a uniform k-subset of V from
+    the words H(seed, TAG_SHARED, 0, c)."""
+    return floyd_subset(n, k, stream(seed, TAG_SHARED, 0))
+
+
+def random_pairs(seed: int, n: int, count: int):
+    """``count`` source/sink pairs, each uniform over the ordered pairs (s, t)
+    with s != t: pair i takes s = bounded(n), b = bounded(n - 1) from the words
+    H(seed, TAG_PAIRS, i, c) and t = b + (b >= s).  Returns int64 arrays."""
+    assert n >= 2
+    s = np.empty(count, np.int64)
+    t = np.empty(count, np.int64)
+    for i in range(count):
+        words = stream(seed, TAG_PAIRS, i)
+        a = lemire_bounded(words, n)
+        b = lemire_bounded(words, n - 1)
+        s[i] = a
+        t[i] = b + (1 if b >= a else 0)
+    return s, t
 
 
 # ---- projection signs, vectorised over edges -------------------------------
