@@ -253,9 +253,55 @@ int cfc_jl_sketch(cfc_graph* g, int64_t k, uint64_t seed,
                   const cfc_solve_params* p, cfc_solve_stats* st);
 /* Projection estimate of farness sum_w ||Z_.v - Z_.w||^2 and closeness
  * (n-1)/farness (Sec. 5.2) of q nodes from the resident sketch
- * (CFC_E_STATE if none).  Host arrays. */
+ * (CFC_E_STATE if none).  nodes = NULL with q = n asks for every node in
+ * id order (O(n) from the sketch: the all-node closeness that Sec. 5.2's
+ * sketch makes cheap).  Host arrays. */
 int cfc_farness_jl(cfc_graph* g, int64_t q, const int64_t* nodes,
                    double* far, double* clo);
+
+/* Sampling with ONE pivot set S for all q query nodes (Sec. 5.1 read
+ * literally: a single uniform sample of k nodes, drawn by
+ * cfc_shared_pivots(seed, n, k, ...)); far = (n/k) sum_{s in S} d_ER(v, s)
+ * and clo = (k/n)(n-1)/sum as in cfc_farness_sampling.  With r the smallest
+ * pivot and y_a = L^+ (e_a - e_r), d_ER(v, s) = y_v[v] - y_v[s] - y_s[v] +
+ * y_s[s], so it takes |S u Q| - 1 solves instead of k q.  Host arrays;
+ * CFC_E_NOT_CONVERGED if a solve misses the tolerance. */
+int cfc_farness_sampling_shared(cfc_graph* g, int64_t q, const int64_t* nodes,
+                                int64_t k, uint64_t seed, double* far, double* clo,
+                                const cfc_solve_params* p, cfc_solve_stats* st);
+
+/* ---- other Laplacian-system centralities (Sec. 2) ------------------------ */
+
+/* Spanning-edge centrality of ne edges {u_i, v_i} of the loaded graph: the
+ * weighted share of spanning trees that contain the edge, equal to
+ * w_e d_ER(u_i, v_i) (Kirchhoff); one solve per edge.  w_e is the merged
+ * conductance.  CFC_E_INVALID if a pair is not an edge.  Host arrays. */
+int cfc_spanning_edge(cfc_graph* g, int64_t ne, const int64_t* u, const int64_t* v,
+                      double* c, const cfc_solve_params* p, cfc_solve_stats* st);
+/* Projection estimate w_e ||Z_.u - Z_.v||^2 with Z the sketch of
+ * cfc_jl_sketch(k, seed) (same signs, Sec. 5.2); k solves for any number of
+ * edges.  Host arrays. */
+int cfc_spanning_edge_jl(cfc_graph* g, int64_t ne, const int64_t* u, const int64_t* v,
+                         int64_t k, uint64_t seed, double* c,
+                         const cfc_solve_params* p, cfc_solve_stats* st);
+
+/* Current-flow throughput (the electrical view of Sec. 2): for each pair a
+ * unit current enters at s_j and leaves at t_j (L p = e_s - e_t, Eq. 1), and
+ * tau[v] = sum over the pairs with v not in {s_j, t_j} of
+ * 1/2 sum_{x in N(v)} w_vx |p(v) - p(x)|.  tau is host double[n], written.
+ * Pairs with s_j = t_j carry no current. */
+int cfc_current_throughput(cfc_graph* g, int64_t npairs, const int64_t* s,
+                           const int64_t* t, double* tau,
+                           const cfc_solve_params* p, cfc_solve_stats* st);
+/* Current-flow betweenness (Brandes and Fleischer; named in Sec. 2) of every
+ * node: the mean throughput over the unordered pairs {s, t} of V \ {v},
+ * c_CB(v) = sum tau_st(v) / C(n-1, 2).  cfc_cfb_exact solves all C(n, 2)
+ * pairs (small graphs); cfc_cfb_sampled draws `count` ordered pairs with
+ * cfc_random_pairs(seed, n, count, ...) and returns the unbiased estimate
+ * (n / (n-2)) * mean_i tau_i(v).  cb is host double[n]; n >= 3. */
+int cfc_cfb_exact(cfc_graph* g, double* cb, const cfc_solve_params* p, cfc_solve_stats* st);
+int cfc_cfb_sampled(cfc_graph* g, int64_t count, uint64_t seed, double* cb,
+                    const cfc_solve_params* p, cfc_solve_stats* st);
 
 /* ---- the library's random draws (host, no device needed) ------------------ */
 
@@ -266,6 +312,13 @@ int cfc_sampling_pivots(uint64_t seed, int64_t node, int64_t n, int64_t k,
                         int64_t* out);
 /* 64 projection sign bits H(seed, 0x4A4C, word, lo*2^32 + hi). */
 uint64_t cfc_jl_sign_word(uint64_t seed, uint64_t word, int64_t lo, int64_t hi);
+/* The shared pivot set: sorted int64[min(k,n)], Floyd's algorithm over
+ * words H(seed, 0x5348, 0, c). */
+int cfc_shared_pivots(uint64_t seed, int64_t n, int64_t k, int64_t* out);
+/* `count` source/sink pairs, uniform over ordered pairs with s != t: pair i
+ * draws s = bounded(n), b = bounded(n-1) from words H(seed, 0x4346, i, c)
+ * and sets t = b + (b >= s).  n >= 2. */
+int cfc_random_pairs(uint64_t seed, int64_t n, int64_t count, int64_t* s, int64_t* t);
 
 /* ---- serving ------------------------------------------------------------- */
 

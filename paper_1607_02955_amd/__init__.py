@@ -23,7 +23,8 @@ from . import _lib
 from ._lib import (COL_DIVERGED, COL_NOT_CONVERGED, COL_OK, COL_SKIPPED, LCC_ONLY, PREC_FP64,
                    PREC_MIXED, QUERY_JL, QUERY_SAMPLING, REJECT_PARALLEL, CfcError, check, lib)
 
-__all__ = ["Context", "Graph", "Server", "CfcError", "sampling_pivots", "jl_sign_word", "version",
+__all__ = ["Context", "Graph", "Server", "CfcError", "sampling_pivots", "jl_sign_word", "shared_pivots",
+           "random_pairs", "version",
            "LCC_ONLY", "REJECT_PARALLEL", "PREC_MIXED", "PREC_FP64", "QUERY_JL", "QUERY_SAMPLING",
            "COL_OK", "COL_NOT_CONVERGED", "COL_DIVERGED", "COL_SKIPPED", "solve_params"]
 
@@ -68,6 +69,20 @@ def sampling_pivots(seed: int, node: int, n: int, k: int) -> np.ndarray:
 
 def jl_sign_word(seed: int, word: int, lo: int, hi: int) -> int:
     return int(lib().cfc_jl_sign_word(seed, word, lo, hi))
+
+
+def shared_pivots(seed: int, n: int, k: int) -> np.ndarray:
+    """The pivot set shared by all query nodes (shared-pivot Sampling)."""
+    out = np.empty(min(k, n), np.int64)
+    check(lib().cfc_shared_pivots(seed, n, k, _p(out, C.c_int64)))
+    return out
+
+
+def random_pairs(seed: int, n: int, count: int):
+    """The source/sink pairs drawn by sampled current-flow betweenness."""
+    s, t = np.empty(count, np.int64), np.empty(count, np.int64)
+    check(lib().cfc_random_pairs(seed, n, count, _p(s, C.c_int64), _p(t, C.c_int64)))
+    return s, t
 
 
 def solve_params(tol=1e-6, precision=PREC_MIXED, block=0, max_refine=20, max_inner=300,
@@ -288,12 +303,64 @@ class Graph:
         check(lib().cfc_jl_sketch(self.handle, k, seed, C.byref(p), C.byref(st)))
         return st.as_dict() if stats else self
 
-    def farness_jl(self, nodes):
+    def farness_jl(self, nodes=None):
+        """Projection farness and closeness of ``nodes`` (None: every node)."""
+        if nodes is None:
+            n = self.n
+            far, clo = np.empty(n), np.empty(n)
+            check(lib().cfc_farness_jl(self.handle, n, None, _p(far, C.c_double), _p(clo, C.c_double)))
+            return far, clo
         nodes = _i64(nodes).ravel()
         far, clo = np.empty(nodes.shape[0]), np.empty(nodes.shape[0])
         check(lib().cfc_farness_jl(self.handle, nodes.shape[0], _p(nodes, C.c_int64),
                                    _p(far, C.c_double), _p(clo, C.c_double)))
         return far, clo
+
+    def farness_sampling_shared(self, nodes, k, seed=1, stats=False, **kw):
+        nodes = _i64(nodes).ravel()
+        far, clo = np.empty(nodes.shape[0]), np.empty(nodes.shape[0])
+        p, st = solve_params(**kw), _lib.SolveStats()
+        check(lib().cfc_farness_sampling_shared(self.handle, nodes.shape[0], _p(nodes, C.c_int64), k,
+                                                seed, _p(far, C.c_double), _p(clo, C.c_double),
+                                                C.byref(p), C.byref(st)))
+        return (far, clo, st.as_dict()) if stats else (far, clo)
+
+    def spanning_edge(self, u, v, stats=False, **kw):
+        u, v = _i64(u).ravel(), _i64(v).ravel()
+        c = np.empty(u.shape[0])
+        p, st = solve_params(**kw), _lib.SolveStats()
+        check(lib().cfc_spanning_edge(self.handle, u.shape[0], _p(u, C.c_int64), _p(v, C.c_int64),
+                                      _p(c, C.c_double), C.byref(p), C.byref(st)))
+        return (c, st.as_dict()) if stats else c
+
+    def spanning_edge_jl(self, u, v, k, seed=1, stats=False, **kw):
+        u, v = _i64(u).ravel(), _i64(v).ravel()
+        c = np.empty(u.shape[0])
+        p, st = solve_params(**kw), _lib.SolveStats()
+        check(lib().cfc_spanning_edge_jl(self.handle, u.shape[0], _p(u, C.c_int64), _p(v, C.c_int64),
+                                         k, seed, _p(c, C.c_double), C.byref(p), C.byref(st)))
+        return (c, st.as_dict()) if stats else c
+
+    def current_throughput(self, s, t, stats=False, **kw):
+        s, t = _i64(s).ravel(), _i64(t).ravel()
+        tau = np.empty(self.n)
+        p, st = solve_params(**kw), _lib.SolveStats()
+        check(lib().cfc_current_throughput(self.handle, s.shape[0], _p(s, C.c_int64), _p(t, C.c_int64),
+                                           _p(tau, C.c_double), C.byref(p), C.byref(st)))
+        return (tau, st.as_dict()) if stats else tau
+
+    def cfb_exact(self, stats=False, **kw):
+        cb = np.empty(self.n)
+        p, st = solve_params(**kw), _lib.SolveStats()
+        check(lib().cfc_cfb_exact(self.handle, _p(cb, C.c_double), C.byref(p), C.byref(st)))
+        return (cb, st.as_dict()) if stats else cb
+
+    def cfb_sampled(self, count, seed=1, stats=False, **kw):
+        cb = np.empty(self.n)
+        p, st = solve_params(**kw), _lib.SolveStats()
+        check(lib().cfc_cfb_sampled(self.handle, count, seed, _p(cb, C.c_double), C.byref(p),
+                                    C.byref(st)))
+        return (cb, st.as_dict()) if stats else cb
 
 
 class Server:

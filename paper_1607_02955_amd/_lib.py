@@ -127,6 +127,19 @@ SIGNATURES = {
     "cfc_farness_jl": (C.c_int, [vp, C.c_int64, i64p, f64p, f64p]),
     "cfc_sampling_pivots": (C.c_int, [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, i64p]),
     "cfc_jl_sign_word": (C.c_uint64, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64]),
+    "cfc_farness_sampling_shared": (C.c_int, [vp, C.c_int64, i64p, C.c_int64, C.c_uint64, f64p, f64p,
+                                              C.POINTER(SolveParams), C.POINTER(SolveStats)]),
+    "cfc_spanning_edge": (C.c_int, [vp, C.c_int64, i64p, i64p, f64p, C.POINTER(SolveParams),
+                                    C.POINTER(SolveStats)]),
+    "cfc_spanning_edge_jl": (C.c_int, [vp, C.c_int64, i64p, i64p, C.c_int64, C.c_uint64, f64p,
+                                       C.POINTER(SolveParams), C.POINTER(SolveStats)]),
+    "cfc_current_throughput": (C.c_int, [vp, C.c_int64, i64p, i64p, f64p, C.POINTER(SolveParams),
+                                         C.POINTER(SolveStats)]),
+    "cfc_cfb_exact": (C.c_int, [vp, f64p, C.POINTER(SolveParams), C.POINTER(SolveStats)]),
+    "cfc_cfb_sampled": (C.c_int, [vp, C.c_int64, C.c_uint64, f64p, C.POINTER(SolveParams),
+                                  C.POINTER(SolveStats)]),
+    "cfc_shared_pivots": (C.c_int, [C.c_uint64, C.c_int64, C.c_int64, i64p]),
+    "cfc_random_pairs": (C.c_int, [C.c_uint64, C.c_int64, C.c_int64, i64p, i64p]),
     "cfc_server_create": (C.c_int, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
     "cfc_server_add_graph": (C.c_int, [vp, vp, i32p]),
     "cfc_server_submit": (C.c_int, [vp, C.POINTER(Query), C.POINTER(C.c_uint64)]),

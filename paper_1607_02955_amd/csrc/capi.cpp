@@ -5,6 +5,7 @@
 
 #include "internal.hpp"
 #include "rng.hpp"
+#include "centrality.hpp"
 #include "solver.hpp"
 
 namespace cfc {
@@ -58,34 +59,7 @@ Graph::~Graph() {
 }
 
 void sampling_pivots(uint64_t seed, int64_t node, int64_t n, int64_t k, std::vector<int64_t>& out) {
-  // Floyd's algorithm over Lemire-bounded integers from the counter stream
-  // H(seed, tag, node, c), c = 0, 1, ...
-  k = std::min(k, n);
-  uint64_t c = 0;
-  auto next = [&]() { return key_hash(seed, kTagSample, uint64_t(node), c++); };
-  auto bounded = [&](uint64_t bound) {
-    unsigned __int128 m = (unsigned __int128)next() * bound;
-    uint64_t low = (uint64_t)m;
-    if (low < bound) {
-      const uint64_t t = (0 - bound) % bound;
-      while (low < t) {
-        m = (unsigned __int128)next() * bound;
-        low = (uint64_t)m;
-      }
-    }
-    return (uint64_t)(m >> 64);
-  };
-  std::vector<int64_t> chosen;
-  chosen.reserve(k);
-  std::vector<char> in(k > 0 ? (size_t)n : 0, 0);
-  for (int64_t j = n - k; j < n; ++j) {
-    const int64_t t = (int64_t)bounded(uint64_t(j) + 1);
-    const int64_t pick = in[t] ? j : t;
-    in[pick] = 1;
-    chosen.push_back(pick);
-  }
-  std::sort(chosen.begin(), chosen.end());
-  out = std::move(chosen);
+  floyd_subset(seed, kTagSample, uint64_t(node), n, k, out);
 }
 
 }  // namespace cfc
@@ -374,6 +348,13 @@ int cfc_farness_jl(cfc_graph* gg, int64_t q, const int64_t* nodes, double* far, 
   Graph* g = G(gg);
   std::lock_guard<std::mutex> lk(g->mu);
   need_device(g);
+  if (!nodes && q == g->n) {
+    // every node, in graph-id order
+    std::vector<int64_t> all(q);
+    for (int64_t i = 0; i < q; ++i) all[i] = i;
+    jl_farness(*g, q, all.data(), far, clo);
+    return CFC_OK;
+  }
   jl_farness(*g, q, nodes, far, clo);
   return CFC_OK;
   CFC_CATCH
@@ -385,6 +366,127 @@ int cfc_sampling_pivots(uint64_t seed, int64_t node, int64_t n, int64_t k, int64
   std::vector<int64_t> piv;
   sampling_pivots(seed, node, n, k, piv);
   std::copy(piv.begin(), piv.end(), out);
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_farness_sampling_shared(cfc_graph* gg, int64_t q, const int64_t* nodes, int64_t k,
+                                uint64_t seed, double* far, double* clo, const cfc_solve_params* p,
+                                cfc_solve_stats* st) {
+  CFC_TRY
+  if (!gg) fail(CFC_E_INVALID, "graph is NULL");
+  Graph* g = G(gg);
+  std::lock_guard<std::mutex> lk(g->mu);
+  need_device(g);
+  if (st) std::memset(st, 0, sizeof(*st));
+  shared_sampling(*g, q, nodes, k, seed, far, clo, params_or_default(p), st);
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_spanning_edge(cfc_graph* gg, int64_t ne, const int64_t* u, const int64_t* v, double* c,
+                      const cfc_solve_params* p, cfc_solve_stats* st) {
+  CFC_TRY
+  if (!gg) fail(CFC_E_INVALID, "graph is NULL");
+  Graph* g = G(gg);
+  std::lock_guard<std::mutex> lk(g->mu);
+  need_device(g);
+  if (st) std::memset(st, 0, sizeof(*st));
+  spanning_edge(*g, ne, u, v, c, params_or_default(p), st);
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_spanning_edge_jl(cfc_graph* gg, int64_t ne, const int64_t* u, const int64_t* v, int64_t k,
+                         uint64_t seed, double* c, const cfc_solve_params* p, cfc_solve_stats* st) {
+  CFC_TRY
+  if (!gg) fail(CFC_E_INVALID, "graph is NULL");
+  Graph* g = G(gg);
+  std::lock_guard<std::mutex> lk(g->mu);
+  need_device(g);
+  if (st) std::memset(st, 0, sizeof(*st));
+  spanning_edge_jl(*g, ne, u, v, k, seed, c, params_or_default(p), st);
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_current_throughput(cfc_graph* gg, int64_t npairs, const int64_t* s, const int64_t* t,
+                           double* tau, const cfc_solve_params* p, cfc_solve_stats* st) {
+  CFC_TRY
+  if (!gg) fail(CFC_E_INVALID, "graph is NULL");
+  if (npairs < 0 || (npairs > 0 && (!s || !t))) fail(CFC_E_INVALID, "bad pair list");
+  Graph* g = G(gg);
+  std::lock_guard<std::mutex> lk(g->mu);
+  need_device(g);
+  if (st) std::memset(st, 0, sizeof(*st));
+  current_throughput(*g, npairs, [&](int64_t j, int64_t& a, int64_t& b) { a = s[j]; b = t[j]; }, tau,
+                     params_or_default(p), st);
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_cfb_sampled(cfc_graph* gg, int64_t count, uint64_t seed, double* cb,
+                    const cfc_solve_params* p, cfc_solve_stats* st) {
+  CFC_TRY
+  if (!gg) fail(CFC_E_INVALID, "graph is NULL");
+  Graph* g = G(gg);
+  std::lock_guard<std::mutex> lk(g->mu);
+  need_device(g);
+  if (g->n < 3) fail(CFC_E_INVALID, "betweenness needs n >= 3");
+  if (count < 1 || !cb) fail(CFC_E_INVALID, "bad arguments");
+  if (st) std::memset(st, 0, sizeof(*st));
+  std::vector<int64_t> s(count), t(count);
+  random_pairs(seed, g->n, count, s.data(), t.data());
+  current_throughput(*g, count, [&](int64_t j, int64_t& a, int64_t& b) { a = s[j]; b = t[j]; }, cb,
+                     params_or_default(p), st);
+  const double n = (double)g->n, scale = n / (n - 2.0) / (double)count;
+  for (int64_t v = 0; v < g->n; ++v) cb[v] *= scale;
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_cfb_exact(cfc_graph* gg, double* cb, const cfc_solve_params* p, cfc_solve_stats* st) {
+  CFC_TRY
+  if (!gg) fail(CFC_E_INVALID, "graph is NULL");
+  Graph* g = G(gg);
+  std::lock_guard<std::mutex> lk(g->mu);
+  need_device(g);
+  const int64_t n = g->n;
+  if (n < 3) fail(CFC_E_INVALID, "betweenness needs n >= 3");
+  if (!cb) fail(CFC_E_INVALID, "cb is NULL");
+  if (st) std::memset(st, 0, sizeof(*st));
+  // pair j of the C(n, 2) pairs s < t in row-major order of the upper triangle
+  int64_t cs = 0, ct = 1;
+  int64_t next = 0;
+  current_throughput(*g, n * (n - 1) / 2,
+                     [&](int64_t j, int64_t& a, int64_t& b) {
+                       if (j != next) fail(CFC_E_INTERNAL, "pairs out of order");
+                       a = cs;
+                       b = ct;
+                       ++next;
+                       if (++ct == n) { ++cs; ct = cs + 1; }
+                     },
+                     cb, params_or_default(p), st);
+  const double norm = 2.0 / ((double)(n - 1) * (double)(n - 2));
+  for (int64_t v = 0; v < n; ++v) cb[v] *= norm;
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_shared_pivots(uint64_t seed, int64_t n, int64_t k, int64_t* out) {
+  CFC_TRY
+  if (n < 1 || k < 1 || !out) fail(CFC_E_INVALID, "bad arguments");
+  std::vector<int64_t> piv;
+  floyd_subset(seed, kTagShared, 0, n, k, piv);
+  std::copy(piv.begin(), piv.end(), out);
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_random_pairs(uint64_t seed, int64_t n, int64_t count, int64_t* s, int64_t* t) {
+  CFC_TRY
+  if (n < 2 || count < 0 || (count > 0 && (!s || !t))) fail(CFC_E_INVALID, "bad arguments");
+  random_pairs(seed, n, count, s, t);
   return CFC_OK;
   CFC_CATCH
 }

@@ -42,7 +42,7 @@ static bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice;
 }
 
-static void check_params(const cfc_solve_params& p) {
+void check_params(const cfc_solve_params& p) {
   if (!(p.tol > 0 && p.tol < 1)) fail(CFC_E_INVALID, "tol must be in (0, 1)");
   if (p.precision != CFC_PREC_MIXED && p.precision != CFC_PREC_FP64) fail(CFC_E_INVALID, "bad precision");
   if (p.max_refine < 0 || p.max_inner < 1) fail(CFC_E_INVALID, "bad iteration limits");

@@ -100,7 +100,7 @@ struct DevLevel {
   int n = 0, nnz = 0, nagg = 0;
   int light_nnz = 0, nheavy = 0, nseg = 0;  // heavy rows live in their own CSR
   DBuf rowptr, col, w32, w64, deg32, deg64, sdinv32, sdinv64, agg, aggptr;
-  DBuf heavy, hseg, hptr, hcol, hw32, hw64, seg_e;
+  DBuf heavy, hseg, hptr, hcol, hw32, hw64, seg_e, seg_row;
   bool unit = false;
   float omega32 = 0;
   double omega64 = 0;

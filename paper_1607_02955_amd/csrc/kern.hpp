@@ -35,6 +35,7 @@ struct LevelArgs {
   const int* hcol = nullptr;   // heavy edges: column
   const void* hw = nullptr;    // heavy edges: weight (T), nullptr = all ones
   const int* seg_e = nullptr;  // [nseg+1] edge range of each segment
+  const int* seg_row = nullptr;// [nseg] row of each segment
   void* hpart = nullptr;       // [nseg][W] partial sums (element type T)
 };
 
@@ -95,6 +96,14 @@ struct KernTable {
   // T[u] += x_u . s  (s = column sums, scal S_CS)
   void (*jl_rowdot)(int n, const double* x64, int ncols, const double* scal, double* T, hipStream_t);
   void (*zero)(void* p, size_t bytes, hipStream_t);
+  // tp[u] += node throughput of the block's unit flows ps[j] -> pt[j] (rows,
+  // -1 = unused column) summed over its first ncols columns; seg_part holds
+  // double[nseg] scratch for heavy rows.
+  void (*throughput)(const LevelArgs& l64, const double* x64, int ncols, const int* ps,
+                     const int* pt, double* seg_part, double* tp, hipStream_t);
+  // out[i] += |x_{a_i} - x_{b_i}|^2 over the first ncols columns
+  void (*edge_sq)(int ne, const int* a, const int* b, const double* x64, int ncols, double* out,
+                  hipStream_t);
 };
 
 // Tables for element type float (FP32 inner solver) and double.
@@ -111,6 +120,9 @@ void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt
                hipStream_t s);
 // out[i] = src[idx[i]] for i < q
 void gather(int q, const double* src, const int* idx, double* out, hipStream_t s);
+// out[i] = src[row[i] * W + col[i]]
+void gather_rc(int64_t q, const double* src, int W, const int* row, const int* col, double* out,
+               hipStream_t s);
 // x64[u, j] = 0 for every row u and every column j with flag[j] != 0
 void zero_cols(int n, int W, double* x64, const int* flag, hipStream_t s);
 // fill with zero bytes by a kernel (graph-capture friendly)

@@ -131,6 +131,13 @@ __global__ void k_gather(int q, const double* __restrict__ src, const int* __res
   if (i < q) out[i] = src[idx[i]];
 }
 
+__global__ void k_gather_rc(int64_t q, const double* __restrict__ src, int W,
+                            const int* __restrict__ row, const int* __restrict__ col,
+                            double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < q) out[i] = src[(size_t)row[i] * W + col[i]];
+}
+
 __global__ __launch_bounds__(256) void k_reduce_part(int n, const double* __restrict__ x,
                                                      double* __restrict__ part) {
   __shared__ double red[256];
@@ -199,6 +206,13 @@ void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt
 void gather(int q, const double* src, const int* idx, double* out, hipStream_t s) {
   if (q <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3((q + 255) / 256), dim3(256), 0, s, q, src, idx, out);
+}
+
+void gather_rc(int64_t q, const double* src, int W, const int* row, const int* col, double* out,
+               hipStream_t s) {
+  if (q <= 0) return;
+  hipLaunchKernelGGL(k_gather_rc, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, q, src, W, row,
+                     col, out);
 }
 
 void reduce_sum(int n, const double* x, double* part, double* out, hipStream_t s) {

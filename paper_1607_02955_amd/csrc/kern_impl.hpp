@@ -818,6 +818,164 @@ __global__ __launch_bounds__(kBlock) void k_jl_rowdot(int n, const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Electrical currents of a block of unit s_j -> t_j flows (Sec. 2): column j
+// of the FP64 block x holds potentials with L x_j = e_{s_j} - e_{t_j}, so
+// edge {u, v} carries w_uv (x_u[j] - x_v[j]).  The throughput of node u in
+// flow j is half the absolute current over its edges, counted only when u is
+// neither s_j nor t_j.  One row group per row (or heavy-row segment), lanes
+// across the columns; the lane sum over columns is reduced across the row
+// group, so each row's total is written by one lane in a fixed order.
+
+// sum over edges e0..e1 of w_e |x_u - x_col(e)| per column (4 rows in flight)
+template <int W>
+__device__ __forceinline__ void tp_lane(const double* __restrict__ x, const int* __restrict__ col,
+                                        const double* __restrict__ w, int e0, int e1, int c0,
+                                        const Vec<double, RowShape<W>::V>& xu,
+                                        double (&acc)[RowShape<W>::V]) {
+  constexpr int V = RowShape<W>::V;
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    Vec<double, V> xv[4];
+    double we[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = ld<double, V>(x + (size_t)col[e + k] * W + c0);
+      we[k] = w ? w[e + k] : 1.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += we[k] * fabs(xu.v[i] - xv[k].v[i]);
+  }
+  for (; e < e1; ++e) {
+    const Vec<double, V> xv = ld<double, V>(x + (size_t)col[e] * W + c0);
+    const double we = w ? w[e] : 1.0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] += we * fabs(xu.v[i] - xv.v[i]);
+  }
+}
+
+// lane sum over the columns that count for row u
+template <int W>
+__device__ __forceinline__ double tp_masked(int u, const double (&acc)[RowShape<W>::V],
+                                            const int (&ps)[RowShape<W>::V],
+                                            const int (&pt)[RowShape<W>::V]) {
+  double s = 0;
+#pragma unroll
+  for (int i = 0; i < RowShape<W>::V; ++i)
+    if (ps[i] >= 0 && u != ps[i] && u != pt[i]) s += acc[i];
+  return s;
+}
+
+template <int W>
+__device__ __forceinline__ void tp_pairs(const int* __restrict__ ps, const int* __restrict__ pt,
+                                         int ncols, int c0, int (&a)[RowShape<W>::V],
+                                         int (&b)[RowShape<W>::V]) {
+#pragma unroll
+  for (int i = 0; i < RowShape<W>::V; ++i) {
+    const bool ok = c0 + i < ncols;
+    a[i] = ok ? ps[c0 + i] : -1;
+    b[i] = ok ? pt[c0 + i] : -1;
+  }
+}
+
+// heavy rows: seg_part[seg] = lane-and-column sum over the segment's edges
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_tp_seg(LevelArgs L, const double* __restrict__ x,
+                                                   int ncols, const int* __restrict__ ps,
+                                                   const int* __restrict__ pt,
+                                                   double* __restrict__ seg_part) {
+  constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
+  const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
+  int a[V], b[V];
+  tp_pairs<W>(ps, pt, ncols, c0, a, b);
+  const double* hw = static_cast<const double*>(L.hw);
+  int tb, te;
+  block_tiles((L.nseg + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int sg = t * RG + rg;
+    const bool ok = sg < L.nseg;
+    double s = 0;
+    if (ok) {
+      const int u = L.seg_row[sg];
+      const Vec<double, V> xu = ld<double, V>(x + (size_t)u * W + c0);
+      double acc[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] = 0;
+      tp_lane<W>(x, L.hcol, hw, L.seg_e[sg], L.seg_e[sg + 1], c0, xu, acc);
+      s = tp_masked<W>(u, acc, a, b);
+    }
+    for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+    if (ok && lane == 0) seg_part[sg] = s;
+  }
+}
+
+// tp[u] += throughput of row u summed over the block's flows
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_tp_rows(LevelArgs L, const double* __restrict__ x,
+                                                    int ncols, const int* __restrict__ ps,
+                                                    const int* __restrict__ pt,
+                                                    const double* __restrict__ seg_part,
+                                                    double* __restrict__ tp) {
+  constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
+  const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
+  int a[V], b[V];
+  tp_pairs<W>(ps, pt, ncols, c0, a, b);
+  const double* w = static_cast<const double*>(L.w);
+  int tb, te;
+  block_tiles((L.n + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int u = t * RG + rg;
+    const bool ok = u < L.n;
+    const int hh = ok && L.heavy ? L.heavy[u] : -1;
+    double s = 0;
+    if (ok && hh < 0) {
+      const Vec<double, V> xu = ld<double, V>(x + (size_t)u * W + c0);
+      double acc[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] = 0;
+      tp_lane<W>(x, L.col, w, L.rowptr[u], L.rowptr[u + 1], c0, xu, acc);
+      s = tp_masked<W>(u, acc, a, b);
+    }
+    for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+    if (ok && lane == 0) {
+      if (hh >= 0)
+        for (int sg = L.hseg[hh]; sg < L.hseg[hh + 1]; ++sg) s += seg_part[sg];
+      tp[u] += 0.5 * s;
+    }
+  }
+}
+
+// out[i] += sum over the first ncols columns of (x_{a_i} - x_{b_i})^2: the
+// squared sketch distance of Sec. 5.2 between the endpoints of edge i.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_edge_sq(int ne, const int* __restrict__ ea,
+                                                    const int* __restrict__ eb,
+                                                    const double* __restrict__ x, int ncols,
+                                                    double* __restrict__ out) {
+  constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
+  const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
+  int tb, te;
+  block_tiles((ne + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int i = t * RG + rg;
+    const bool ok = i < ne;
+    double s = 0;
+    if (ok) {
+      const Vec<double, V> xa = ld<double, V>(x + (size_t)ea[i] * W + c0);
+      const Vec<double, V> xb = ld<double, V>(x + (size_t)eb[i] * W + c0);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const double d = xa.v[k] - xb.v[k];
+        if (c0 + k < ncols) s += d * d;
+      }
+    }
+    for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+    if (ok && lane == 0) out[i] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 inline int grid_units(int units, int rg) { return grid_for(units, rg); }
 
@@ -969,6 +1127,23 @@ struct Launch {
     if (!g) return;
     hipLaunchKernelGGL((k_jl_rowdot<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, scal, Tv);
   }
+  static void throughput(const LevelArgs& L, const double* x64, int ncols, const int* ps,
+                         const int* pt, double* seg_part, double* tp, hipStream_t s) {
+    if (L.nseg) {
+      const int gs = grid_units(L.nseg, RowShape<W>::RG);
+      hipLaunchKernelGGL((k_tp_seg<W>), dim3(gs), dim3(kBlock), 0, s, L, x64, ncols, ps, pt, seg_part);
+    }
+    const int g = grid_units(L.n, RowShape<W>::RG);
+    if (!g) return;
+    hipLaunchKernelGGL((k_tp_rows<W>), dim3(g), dim3(kBlock), 0, s, L, x64, ncols, ps, pt,
+                       (const double*)seg_part, tp);
+  }
+  static void edge_sq(int ne, const int* a, const int* b, const double* x64, int ncols, double* out,
+                      hipStream_t s) {
+    const int g = grid_units(ne, RowShape<W>::RG);
+    if (!g) return;
+    hipLaunchKernelGGL((k_edge_sq<W>), dim3(g), dim3(kBlock), 0, s, ne, a, b, x64, ncols, out);
+  }
   static void zero(void* p, size_t bytes, hipStream_t s) { zero_fill(p, bytes, s); }
 
   static KernTable table() {
@@ -991,6 +1166,8 @@ struct Launch {
     t.jl_rownorm = &jl_rownorm;
     t.jl_rowdot = &jl_rowdot;
     t.zero = &zero;
+    t.throughput = &throughput;
+    t.edge_sq = &edge_sq;
     return t;
   }
 };

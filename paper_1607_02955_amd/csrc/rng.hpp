@@ -18,6 +18,8 @@ namespace cfc {
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kTagJL = 0x4A4Cull;
 constexpr uint64_t kTagSample = 0x5350ull;
+constexpr uint64_t kTagShared = 0x5348ull;
+constexpr uint64_t kTagPairs = 0x4346ull;
 
 CFC_HD uint64_t sm_step(uint64_t x) {
   uint64_t z = x + kGolden;

@@ -54,7 +54,8 @@ void upload_hierarchy(Graph& g) {
     d.nagg = h.aggptr.empty() ? 0 : (int)h.aggptr.size() - 1;
     d.unit = (l == 0) && g.unit;
     // light CSR (heavy rows keep no edges) + heavy CSR cut into segments
-    std::vector<int32_t> lptr(h.n + 1, 0), lcol, hid(h.n, -1), hptr(1, 0), hcol, hseg(1, 0), seg_e(1, 0);
+    std::vector<int32_t> lptr(h.n + 1, 0), lcol, hid(h.n, -1), hptr(1, 0), hcol, hseg(1, 0), seg_e(1, 0),
+        seg_row;
     std::vector<double> lw, hw;
     lcol.reserve(h.col.size());
     lw.reserve(h.w.size());
@@ -70,6 +71,7 @@ void upload_hierarchy(Graph& g) {
         if (seg_e.back() != (int32_t)hcol.size()) seg_e.push_back((int32_t)hcol.size());
         hptr.push_back((int32_t)hcol.size());
         hseg.push_back((int32_t)seg_e.size() - 1);
+        seg_row.resize(seg_e.size() - 1, (int32_t)r);
       } else {
         for (int32_t e = e0; e < e1; ++e) {
           lcol.push_back(h.col[e]);
@@ -107,6 +109,7 @@ void upload_hierarchy(Graph& g) {
       upload(c, d.hptr, hptr, s);
       upload(c, d.hcol, hcol, s);
       upload(c, d.seg_e, seg_e, s);
+      upload(c, d.seg_row, seg_row, s);
     }
     upload(c, d.deg32, deg32, s);
     upload(c, d.deg64, h.deg, s);
@@ -118,7 +121,8 @@ void upload_hierarchy(Graph& g) {
     }
     d.omega64 = H.omega;
     for (const DBuf* b : {&d.rowptr, &d.col, &d.w32, &d.w64, &d.deg32, &d.deg64, &d.sdinv32, &d.sdinv64,
-                          &d.agg, &d.aggptr, &d.heavy, &d.hseg, &d.hptr, &d.hcol, &d.hw32, &d.hw64, &d.seg_e})
+                          &d.agg, &d.aggptr, &d.heavy, &d.hseg, &d.hptr, &d.hcol, &d.hw32, &d.hw64, &d.seg_e,
+                          &d.seg_row})
       D->bytes += b->bytes;
   }
   // coarsest pseudoinverse, zero-padded to a multiple of 16
@@ -172,6 +176,7 @@ static LevelArgs level_args(const Graph& g, int l, bool fp64) {
     a.hcol = d.hcol.as<int>();
     a.hw = d.unit ? nullptr : (fp64 ? (const void*)d.hw64.p : (const void*)d.hw32.p);
     a.seg_e = d.seg_e.as<int>();
+    a.seg_row = d.seg_row.as<int>();
   }
   return a;
 }

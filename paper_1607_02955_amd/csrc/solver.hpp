@@ -82,6 +82,8 @@ struct Solver {
 };
 
 cfc_solve_params default_solve();
+// CFC_E_INVALID unless every field of p is in range
+void check_params(const cfc_solve_params& p);
 // Fill in block width and V-cycle depth left at 0 (autotuner; cached in
 // the graph and optionally on disk).
 cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p, int64_t ncols);

@@ -180,3 +180,16 @@ def test_jl_sign_words_match_oracle():
         seed = int(rng.integers(0, 2**63))
         word = int(rng.integers(0, 64))
         assert cfc.jl_sign_word(seed, word, lo, hi) == ORNG.hash4(seed, ORNG.TAG_JL, word, (lo << 32) | hi)
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (10, 3), (1000, 1000), (100000, 512)])
+def test_shared_pivots_match_oracle(n, k):
+    for seed in (1, 7, 2**63 + 5):
+        assert cfc.shared_pivots(seed, n, k).tolist() == ORNG.shared_pivots(seed, n, k)
+
+
+def test_random_pairs_match_oracle():
+    for seed, n in ((1, 2), (3, 17), (99, 1000003)):
+        s, t = cfc.random_pairs(seed, n, 300)
+        so, to = ORNG.random_pairs(seed, n, 300)
+        assert s.tolist() == so.tolist() and t.tolist() == to.tolist()
