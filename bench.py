@@ -11,6 +11,13 @@ the farness of 100 query nodes.  The metric is solved right-hand sides per
 second; inputs are resident in HBM when the timed region starts (the graph
 hierarchy is set up once, outside the timed region).
 
+Other workloads (--workload): grid32_exact (exact farness, 32x32 grid, FP64
+to 1e-10), rmat20_sampling (Sampling, 1000 pivots x 64 nodes, R-MAT scale 20),
+road2048_jl256 (projection k = 256 on a perturbed 2048^2 road grid),
+ba100k_shared1000 (shared-pivot Sampling), ba100k_cfb4096 (sampled
+current-flow betweenness), ba100k_spanning_jl512 (projection spanning-edge
+centrality of every edge) and serve_mix (the serving loop).
+
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (algorithmic bytes per launch over its HIP-event-timed duration on the launch
 stream), the CPU oracle timed on a bounded sample, and the plain FP64
@@ -72,6 +79,18 @@ def make_workload(name):
     if name == "road2048_jl256":
         g = synth.cached("road2048", synth.road_grid, 2048, seed=1)
         return g, dict(kind="jl", k=256, block=0, tol=1e-6, queries=32)
+    if name == "ba100k_shared1000":
+        # one shared set of 1000 pivots for 100 query nodes: 1099 solves
+        g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
+        return g, dict(kind="shared", k=1000, block=0, tol=1e-6, queries=100)
+    if name == "ba100k_cfb4096":
+        # sampled current-flow betweenness of every node from 4096 random pairs
+        g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
+        return g, dict(kind="cfb", k=4096, block=512, tol=1e-6, queries=0)
+    if name == "ba100k_spanning_jl512":
+        # projection spanning-edge centrality of all 399,990 edges, k = 512
+        g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
+        return g, dict(kind="spanning_jl", k=512, block=512, tol=1e-6, queries=0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -185,7 +204,19 @@ def cpu_baseline(eg, spec, budget_s=20.0):
     try:
         if ctxm:
             ctxm.__enter__()
-        if spec["kind"] == "jl":
+        if spec["kind"] == "cfb":
+            from oracle import betweenness as CB
+            t0 = time.perf_counter()
+            done, cnt = 0, 4
+            while time.perf_counter() - t0 < budget_s and done < spec["k"]:
+                CB.cfb_sampled(L, eg, cnt, seed=1 + done, tol=spec["tol"])
+                done += cnt
+                cnt = min(cnt * 2, 64)
+            dt = time.perf_counter() - t0
+            return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",
+                    "sample": f"{done} random source/sink pairs: oracle Jacobi-PCG (FP64) to rel. "
+                              f"residual {spec['tol']:g} plus node throughput, {dt:.1f} s"}
+        if spec["kind"] in ("jl", "spanning_jl"):
             Y = E.projection_rhs(eg, spec["k"], seed=1)
             cols = 1
             t0 = time.perf_counter()
@@ -286,6 +317,15 @@ def main():
         if spec["kind"] == "sampling":
             _, _, st = g.farness_sampling(nodes, spec["k"], seed=seed, stats=True, **kw2)
             return st, st["columns"]
+        if spec["kind"] == "shared":
+            _, _, st = g.farness_sampling_shared(nodes, spec["k"], seed=seed, stats=True, **kw2)
+            return st, st["columns"]
+        if spec["kind"] == "cfb":
+            _, st = g.cfb_sampled(spec["k"], seed=seed, stats=True, **kw2)
+            return st, st["columns"]
+        if spec["kind"] == "spanning_jl":
+            _, st = g.spanning_edge_jl(eg.u, eg.v, spec["k"], seed=seed, stats=True, **kw2)
+            return st, spec["k"]
         _, _, st = g.farness_exact(nodes, stats=True, **kw2)
         return st, st["columns"]
 

@@ -78,8 +78,12 @@ void random_pairs(uint64_t seed, int64_t n, int64_t count, int64_t* s, int64_t* 
   }
 }
 
-double edge_weight(const Graph& g, int64_t u, int64_t v) {
+double edge_weight(const Graph& g, int64_t u, int64_t v, int64_t hint) {
   if (u < 0 || u >= g.n || v < 0 || v >= g.n || u == v) fail(CFC_E_INVALID, "not an edge of the graph");
+  // edge lists passed in the graph's own canonical order hit directly
+  if (hint >= 0 && hint < (int64_t)g.eu.size() &&
+      ((g.eu[hint] == u && g.ev[hint] == v) || (g.eu[hint] == v && g.ev[hint] == u)))
+    return g.ew[hint];
   // search the shorter of the two sorted rows
   if (g.rowptr[u + 1] - g.rowptr[u] > g.rowptr[v + 1] - g.rowptr[v]) std::swap(u, v);
   const int32_t* b = g.col.data() + g.rowptr[u];
@@ -211,7 +215,7 @@ void spanning_edge(Graph& g, int64_t ne, const int64_t* u, const int64_t* v, dou
                    const cfc_solve_params& p, cfc_solve_stats* st) {
   if (ne < 0 || (ne > 0 && (!u || !v || !c))) fail(CFC_E_INVALID, "bad edge list");
   std::vector<double> we(ne);
-  for (int64_t i = 0; i < ne; ++i) we[i] = edge_weight(g, u[i], v[i]);
+  for (int64_t i = 0; i < ne; ++i) we[i] = edge_weight(g, u[i], v[i], i);
   std::vector<int32_t> status(ne);
   pair_solves(g, ne, u, v, c, p, st, status.data());
   require_converged(status, (int)std::min<int64_t>(ne, INT32_MAX));
@@ -227,7 +231,7 @@ void spanning_edge_jl(Graph& g, int64_t ne, const int64_t* u, const int64_t* v, 
   std::vector<double> we(ne);
   std::vector<int32_t> ea(ne), eb(ne);
   for (int64_t i = 0; i < ne; ++i) {
-    we[i] = edge_weight(g, u[i], v[i]);
+    we[i] = edge_weight(g, u[i], v[i], i);
     ea[i] = g.H.perm[u[i]];
     eb[i] = g.H.perm[v[i]];
   }

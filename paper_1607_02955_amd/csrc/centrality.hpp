@@ -15,8 +15,9 @@ void floyd_subset(uint64_t seed, uint64_t tag, uint64_t a, int64_t n, int64_t k,
 // Pair i: s = bounded(n), b = bounded(n - 1) from H(seed, 0x4346, i, c),
 // t = b + (b >= s): uniform over ordered pairs with s != t.
 void random_pairs(uint64_t seed, int64_t n, int64_t count, int64_t* s, int64_t* t);
-// Conductance of edge {u, v} of the loaded graph (CFC_E_INVALID if absent).
-double edge_weight(const Graph& g, int64_t u, int64_t v);
+// Conductance of edge {u, v} of the loaded graph (CFC_E_INVALID if absent);
+// `hint` = index of the edge in the canonical list if the caller follows it.
+double edge_weight(const Graph& g, int64_t u, int64_t v, int64_t hint = -1);
 
 void shared_sampling(Graph& g, int64_t q, const int64_t* nodes, int64_t k, uint64_t seed, double* far,
                      double* clo, const cfc_solve_params& p, cfc_solve_stats* st);

@@ -879,34 +879,40 @@ __device__ __forceinline__ void tp_pairs(const int* __restrict__ ps, const int* 
   }
 }
 
-// heavy rows: seg_part[seg] = lane-and-column sum over the segment's edges
+// heavy rows: seg_part[seg] = lane-and-column sum over the segment's edges.
+// A whole workgroup takes one segment (its RG row groups split the edges),
+// since the few long rows would otherwise leave most of the chip idle.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_tp_seg(LevelArgs L, const double* __restrict__ x,
                                                    int ncols, const int* __restrict__ ps,
                                                    const int* __restrict__ pt,
                                                    double* __restrict__ seg_part) {
   constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
+  __shared__ double red[RG];
   const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
   int a[V], b[V];
   tp_pairs<W>(ps, pt, ncols, c0, a, b);
   const double* hw = static_cast<const double*>(L.hw);
-  int tb, te;
-  block_tiles((L.nseg + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
-  for (int t = tb; t < te; ++t) {
-    const int sg = t * RG + rg;
-    const bool ok = sg < L.nseg;
-    double s = 0;
-    if (ok) {
-      const int u = L.seg_row[sg];
-      const Vec<double, V> xu = ld<double, V>(x + (size_t)u * W + c0);
-      double acc[V];
+  for (int sg = blockIdx.x; sg < L.nseg; sg += gridDim.x) {
+    const int u = L.seg_row[sg];
+    const int e0 = L.seg_e[sg], e1 = L.seg_e[sg + 1];
+    const int len = e1 - e0, per = (len + RG - 1) / RG;
+    const int f0 = e0 + min(len, rg * per), f1 = e0 + min(len, (rg + 1) * per);
+    const Vec<double, V> xu = ld<double, V>(x + (size_t)u * W + c0);
+    double acc[V];
 #pragma unroll
-      for (int i = 0; i < V; ++i) acc[i] = 0;
-      tp_lane<W>(x, L.hcol, hw, L.seg_e[sg], L.seg_e[sg + 1], c0, xu, acc);
-      s = tp_masked<W>(u, acc, a, b);
-    }
+    for (int i = 0; i < V; ++i) acc[i] = 0;
+    tp_lane<W>(x, L.hcol, hw, f0, f1, c0, xu, acc);
+    double s = tp_masked<W>(u, acc, a, b);
     for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
-    if (ok && lane == 0) seg_part[sg] = s;
+    if (lane == 0) red[rg] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int i = 0; i < RG; ++i) t += red[i];
+      seg_part[sg] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -1130,7 +1136,7 @@ struct Launch {
   static void throughput(const LevelArgs& L, const double* x64, int ncols, const int* ps,
                          const int* pt, double* seg_part, double* tp, hipStream_t s) {
     if (L.nseg) {
-      const int gs = grid_units(L.nseg, RowShape<W>::RG);
+      const int gs = std::min(L.nseg, 4 * kMaxGrid);
       hipLaunchKernelGGL((k_tp_seg<W>), dim3(gs), dim3(kBlock), 0, s, L, x64, ncols, ps, pt, seg_part);
     }
     const int g = grid_units(L.n, RowShape<W>::RG);
