@@ -102,7 +102,8 @@ typedef struct {
   double setup_ms;                 /* host hierarchy build time */
   uint64_t device_bytes;           /* device memory held by the graph */
   int32_t max_degree;
-  int32_t pad;
+  int32_t eliminated;              /* nodes removed by the elimination level
+                                      (0 = none) */
 } cfc_graph_info;
 
 typedef struct {
@@ -113,6 +114,14 @@ typedef struct {
   double omega;          /* Jacobi smoothing weight (0.8) */
   double mu;             /* coarse-correction scale, 0 < mu < 2 (1.5) */
   uint64_t seed;         /* test-vector seed (1) */
+  int32_t eliminate;     /* low-degree elimination level (Sec. 3.1: LAMG
+                            alternates elimination and aggregation): an
+                            independent set of degree-1 and degree-2 nodes
+                            is removed exactly by a Schur complement before
+                            aggregating.  0 = off, 1 = when it removes at
+                            least 5% of the nodes (default), 2 = whenever
+                            any node qualifies */
+  int32_t pad;
 } cfc_setup_params;
 
 typedef struct {
@@ -171,6 +180,13 @@ typedef struct {
   const int32_t* agg_ptr;   /* [n_coarse+1] aggregate row ranges (contiguous) */
   const int32_t* perm;      /* level 0 only: graph node id -> row */
   const double* coarse_pinv;/* coarsest level only: dense L_c^+ [n*n] */
+  /* Elimination level (n_coarse < n, agg = NULL): rows [0, n_coarse) are
+   * kept and are rows [0, n_coarse) of the next level, whose Laplacian is
+   * the Schur complement; rows [n_coarse, n) are eliminated, each with at
+   * most two kept neighbours elim_nb[2 (r - n_coarse) + i] (-1 = none). */
+  int32_t elimination;      /* 1 on an elimination level, else 0 */
+  int32_t pad;
+  const int32_t* elim_nb;
 } cfc_level_view;
 
 /* ---- context ---------------------------------------------------------------- */

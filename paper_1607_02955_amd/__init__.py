@@ -92,8 +92,9 @@ def solve_params(tol=1e-6, precision=PREC_MIXED, block=0, max_refine=20, max_inn
 
 
 def setup_params(coarsest_max=512, agg_cap=8, test_vectors=8, relax_sweeps=8, omega=0.8,
-                 mu=1.5, seed=1) -> _lib.SetupParams:
-    return _lib.SetupParams(coarsest_max, agg_cap, test_vectors, relax_sweeps, omega, mu, seed)
+                 mu=1.5, seed=1, eliminate=1) -> _lib.SetupParams:
+    return _lib.SetupParams(coarsest_max, agg_cap, test_vectors, relax_sweeps, omega, mu, seed,
+                            eliminate, 0)
 
 
 class Context:
@@ -202,7 +203,8 @@ class Graph:
         return {"n": i.n, "m": i.m, "input_n": i.input_n, "levels": L,
                 "unit_weights": bool(i.unit_weights), "level_n": list(i.level_n[:L]),
                 "level_nnz": list(i.level_nnz[:L]), "operator_complexity": i.operator_complexity,
-                "setup_ms": i.setup_ms, "device_bytes": i.device_bytes, "max_degree": i.max_degree}
+                "setup_ms": i.setup_ms, "device_bytes": i.device_bytes, "max_degree": i.max_degree,
+                "eliminated": i.eliminated}
 
     def node_map(self) -> np.ndarray:
         out = np.empty(self.n, np.int64)
@@ -231,6 +233,8 @@ class Graph:
                "perm": arr(v.perm, n, np.int32)}
         cp = arr(v.coarse_pinv, n * n, np.float64)
         out["coarse_pinv"] = None if cp is None else cp.reshape(n, n)
+        out["elimination"] = bool(v.elimination)
+        out["elim_nb"] = arr(v.elim_nb, 2 * (n - nc), np.int32) if v.elimination else None
         return out
 
     # ---- solves ----

@@ -37,13 +37,13 @@ class GraphInfo(C.Structure):
                 ("unit_weights", C.c_int32), ("level_n", C.c_int64 * MAX_LEVELS),
                 ("level_nnz", C.c_int64 * MAX_LEVELS), ("operator_complexity", C.c_double),
                 ("setup_ms", C.c_double), ("device_bytes", C.c_uint64), ("max_degree", C.c_int32),
-                ("pad", C.c_int32)]
+                ("eliminated", C.c_int32)]
 
 
 class SetupParams(C.Structure):
     _fields_ = [("coarsest_max", C.c_int32), ("agg_cap", C.c_int32), ("test_vectors", C.c_int32),
                 ("relax_sweeps", C.c_int32), ("omega", C.c_double), ("mu", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("eliminate", C.c_int32), ("pad", C.c_int32)]
 
 
 class SolveParams(C.Structure):
@@ -73,7 +73,8 @@ class LevelView(C.Structure):
                 ("row_ptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
                 ("w", C.POINTER(C.c_double)), ("deg", C.POINTER(C.c_double)),
                 ("agg", C.POINTER(C.c_int32)), ("agg_ptr", C.POINTER(C.c_int32)),
-                ("perm", C.POINTER(C.c_int32)), ("coarse_pinv", C.POINTER(C.c_double))]
+                ("perm", C.POINTER(C.c_int32)), ("coarse_pinv", C.POINTER(C.c_double)),
+                ("elimination", C.c_int32), ("pad", C.c_int32), ("elim_nb", C.POINTER(C.c_int32))]
 
 
 class ServerOpts(C.Structure):

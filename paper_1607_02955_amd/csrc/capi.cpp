@@ -167,6 +167,7 @@ int cfc_graph_get_info(const cfc_graph* gg, cfc_graph_info* out) {
   out->input_n = g->input_n;
   out->unit_weights = g->unit ? 1 : 0;
   out->max_degree = g->max_degree;
+  if (g->have_h && g->H.lv[0].nC > 0) out->eliminated = (int32_t)(g->H.lv[0].n - g->H.lv[0].nC);
   if (g->have_h) {
     out->levels = (int32_t)g->H.lv.size();
     double num = 0, den = 0;
@@ -220,7 +221,9 @@ int cfc_hierarchy_level(const cfc_graph* gg, int32_t level, cfc_level_view* out)
   std::memset(out, 0, sizeof(*out));
   out->n = h.n;
   out->nnz = h.nnz();
-  out->n_coarse = h.aggptr.empty() ? 0 : (int64_t)h.aggptr.size() - 1;
+  out->n_coarse = h.nC > 0 ? h.nC : (h.aggptr.empty() ? 0 : (int64_t)h.aggptr.size() - 1);
+  out->elimination = h.nC > 0 ? 1 : 0;
+  out->elim_nb = h.nC > 0 ? h.enb.data() : nullptr;
   out->row_ptr = h.rowptr.data();
   out->col = h.col.data();
   out->w = h.w.data();

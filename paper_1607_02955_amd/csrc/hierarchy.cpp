@@ -17,6 +17,13 @@
 //     on every level (restriction and prolongation then need no atomics),
 //     ordered along a Cuthill-McKee sweep of the fine graph so that
 //     neighbouring rows stay close in memory;
+//   * optionally first an elimination level (LAMG alternates elimination and
+//     aggregation, Sec. 3.1): an independent set F of degree-1 and degree-2
+//     nodes is removed exactly.  Ordering the kept nodes C first,
+//     L = [L_CC L_CF; L_FC D_F] with D_F diagonal, and the Schur complement
+//     L_CC - L_CF D_F^-1 L_FC is again a graph Laplacian on C: a degree-1 node
+//     takes its edge with it, a degree-2 node with neighbours a, b is replaced
+//     by the series edge {a, b} of conductance w_a w_b / (w_a + w_b);
 //   * the coarsest level's dense pseudoinverse L_c^+ = Pi G Pi, with G the
 //     inverse of L_c grounded at node 0 (Sec. 4, last paragraph) padded with
 //     a zero row and column, and Pi = I - 11^T / n_c.
@@ -40,6 +47,8 @@ cfc_setup_params default_setup() {
   p.omega = 0.8;
   p.mu = 1.5;
   p.seed = 1;
+  p.eliminate = 1;
+  p.pad = 0;
   return p;
 }
 
@@ -51,7 +60,75 @@ struct BLevel {  // a level in build numbering
   std::vector<double> w, deg;
   std::vector<int32_t> agg;  // to next level (build numbering)
   int64_t nagg = 0;
+  // elimination level: cidx[u] = u's node on the next level, -1 if eliminated
+  std::vector<int32_t> cidx;
+  std::vector<int32_t> F;    // eliminated nodes
 };
+
+// Choose an independent set of degree-1 nodes, then degree-2 nodes (in id
+// order), and form the Schur complement graph on the rest.  Returns false
+// when the mode's threshold is not met (mode 1: at least 5% of the nodes).
+bool eliminate(BLevel& B, int mode, BLevel& R) {
+  const int64_t n = B.n;
+  if (mode == 0 || n < 3) return false;
+  std::vector<char> blocked(n, 0);
+  std::vector<int32_t> F;
+  for (int d = 1; d <= 2; ++d)
+    for (int64_t u = 0; u < n; ++u) {
+      if (blocked[u] || B.rowptr[u + 1] - B.rowptr[u] != d) continue;
+      if (n - (int64_t)F.size() <= 2) break;  // keep at least two nodes
+      F.push_back((int32_t)u);
+      blocked[u] = 1;
+      for (int32_t e = B.rowptr[u]; e < B.rowptr[u + 1]; ++e) blocked[B.col[e]] = 1;
+    }
+  if (F.empty() || (mode == 1 && (double)F.size() < 0.05 * (double)n)) return false;
+  std::vector<char> isF(n, 0);
+  for (int32_t f : F) isF[f] = 1;
+  B.cidx.assign(n, -1);
+  int64_t nc = 0;
+  for (int64_t u = 0; u < n; ++u)
+    if (!isF[u]) B.cidx[u] = (int32_t)nc++;
+  R.n = nc;
+  R.rowptr.assign(nc + 1, 0);
+  R.deg.assign(nc, 0.0);
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t u = 0; u < n; ++u) {
+    if (isF[u]) continue;
+    row.clear();
+    for (int32_t e = B.rowptr[u]; e < B.rowptr[u + 1]; ++e) {
+      const int32_t v = B.col[e];
+      if (!isF[v]) {
+        row.emplace_back(B.cidx[v], B.w[e]);
+        continue;
+      }
+      if (B.rowptr[v + 1] - B.rowptr[v] != 2) continue;  // degree 1: the edge goes
+      // degree 2: series edge to v's other neighbour
+      const int32_t e0 = B.rowptr[v];
+      const int32_t o = B.col[e0] == u ? e0 + 1 : e0;
+      const double wa = B.w[e], wb = B.w[o];
+      row.emplace_back(B.cidx[B.col[o]], wa * wb / (wa + wb));
+    }
+    std::sort(row.begin(), row.end());
+    const int64_t c = B.cidx[u];
+    for (size_t i = 0; i < row.size(); ++i) {
+      if (i && row[i].first == row[i - 1].first) {
+        R.w.back() += row[i].second;  // parallel conductances add
+        continue;
+      }
+      R.col.push_back(row[i].first);
+      R.w.push_back(row[i].second);
+    }
+    R.rowptr[c + 1] = (int32_t)R.col.size();
+  }
+  for (int64_t c = 0; c < nc; ++c) {
+    double sacc = 0;
+    for (int32_t e = R.rowptr[c]; e < R.rowptr[c + 1]; ++e) sacc += R.w[e];
+    R.deg[c] = sacc;
+  }
+  B.F = std::move(F);
+  B.nagg = nc;
+  return true;
+}
 
 constexpr uint64_t kTagTestVec = 0x5456ull;
 
@@ -321,12 +398,17 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   if (p.relax_sweeps < 0 || p.relax_sweeps > 100) fail(CFC_E_INVALID, "relax_sweeps must be in [0, 100]");
   if (!(p.omega > 0 && p.omega < 1)) fail(CFC_E_INVALID, "omega must be in (0, 1)");
   if (!(p.mu > 0 && p.mu < 2)) fail(CFC_E_INVALID, "mu must be in (0, 2)");
+  if (p.eliminate < 0 || p.eliminate > 2) fail(CFC_E_INVALID, "eliminate must be 0, 1 or 2");
   std::vector<BLevel> B(1);
   B[0].n = g.n;
   B[0].rowptr = g.rowptr;
   B[0].col = g.col;
   B[0].w = g.w;
   B[0].deg = g.deg;
+  {
+    BLevel R;
+    if (B[0].n > p.coarsest_max && eliminate(B[0], p.eliminate, R)) B.push_back(std::move(R));
+  }
   while (B.back().n > p.coarsest_max && (int)B.size() < CFC_MAX_LEVELS) {
     BLevel& F = B.back();
     std::vector<int32_t> agg;
@@ -347,7 +429,9 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   for (int l = 0; l + 1 < L; ++l) {
     key[l + 1].assign(B[l + 1].n, INT64_MAX);
     for (int64_t u = 0; u < B[l].n; ++u) {
-      int64_t& k = key[l + 1][B[l].agg[u]];
+      const int32_t to = B[l].cidx.empty() ? B[l].agg[u] : B[l].cidx[u];
+      if (to < 0) continue;
+      int64_t& k = key[l + 1][to];
       k = std::min(k, key[l][u]);
     }
   }
@@ -361,6 +445,22 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
                    [&](int32_t a, int32_t b) { return key[L - 1][a] < key[L - 1][b]; });
   for (int l = L - 2; l >= 0; --l) {
     const BLevel& F = B[l];
+    if (!F.cidx.empty()) {
+      // elimination level: kept nodes in the next level's order, then the
+      // eliminated ones next to their first neighbour
+      std::vector<int32_t> cnode(B[l + 1].n);
+      for (int64_t u = 0; u < F.n; ++u)
+        if (F.cidx[u] >= 0) cnode[F.cidx[u]] = (int32_t)u;
+      std::vector<int32_t> rowc(B[l + 1].n);
+      for (int64_t i = 0; i < B[l + 1].n; ++i) rowc[order[l + 1][i]] = (int32_t)i;
+      order[l].reserve(F.n);
+      for (int32_t c : order[l + 1]) order[l].push_back(cnode[c]);
+      std::vector<std::pair<int64_t, int32_t>> fk;
+      for (int32_t f : F.F) fk.emplace_back((int64_t)rowc[F.cidx[F.col[F.rowptr[f]]]] * F.n + f, f);
+      std::sort(fk.begin(), fk.end());
+      for (auto& x : fk) order[l].push_back(x.second);
+      continue;
+    }
     std::vector<int32_t> start(F.nagg + 1, 0), mem(F.n);
     for (int64_t u = 0; u < F.n; ++u) start[F.agg[u] + 1]++;
     for (int64_t i = 0; i < F.nagg; ++i) start[i + 1] += start[i];
@@ -399,7 +499,40 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
       O.rowptr[r + 1] = (int32_t)O.col.size();
       O.deg[r] = F.deg[old];
     }
-    if (l + 1 < L) {
+    if (!F.cidx.empty()) {
+      // forward operator over kept rows and the eliminated rows' neighbours
+      const int64_t nc = F.nagg;
+      O.nC = nc;
+      O.fptr.assign(nc + 1, 0);
+      O.enb.assign(2 * (F.n - nc), -1);
+      O.ew.assign(2 * (F.n - nc), 0.0);
+      O.einv.assign(F.n - nc, 0.0);
+      std::vector<std::pair<int32_t, double>> fr;
+      for (int64_t r = 0; r < F.n; ++r) {
+        const int32_t old = order[l][r];
+        if (r < nc) {
+          fr.clear();
+          for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e) {
+            const int32_t v = F.col[e];
+            if (F.cidx[v] < 0) fr.emplace_back(newid[l][v], F.w[e] / F.deg[v]);
+          }
+          std::sort(fr.begin(), fr.end());
+          for (auto& x : fr) { O.fcol.push_back(x.first); O.fcoef.push_back(x.second); }
+          O.fptr[r + 1] = (int32_t)O.fcol.size();
+        } else {
+          const int64_t i = r - nc;
+          int k = 0;
+          for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e, ++k) {
+            O.enb[2 * i + k] = newid[l][F.col[e]];
+            O.ew[2 * i + k] = F.w[e];
+          }
+          O.einv[i] = 1.0 / F.deg[old];
+        }
+      }
+      for (int64_t r = 0; r < nc; ++r)
+        if (F.cidx[order[l][r]] < 0 || newid[l + 1][F.cidx[order[l][r]]] != r)
+          fail(CFC_E_INTERNAL, "kept rows are not the next level's rows");
+    } else if (l + 1 < L) {
       O.agg.resize(F.n);
       for (int64_t r = 0; r < F.n; ++r) O.agg[r] = newid[l + 1][F.agg[order[l][r]]];
       O.aggptr.assign(F.nagg + 1, 0);

@@ -83,6 +83,14 @@ struct HostLevel {
   std::vector<double> deg;           // D_ii
   std::vector<int32_t> agg;          // row -> next-level node (empty on coarsest)
   std::vector<int32_t> aggptr;       // next-level node -> row range
+  // Elimination level (nC > 0): rows [0, nC) are kept and are the next
+  // level's rows; rows [nC, n) are eliminated.  Forward operator over kept
+  // rows: fptr/fcol/fcoef (coefficient w_cf / d_f of eliminated row f);
+  // eliminated row f: kept neighbours enb[2 (f - nC) + i] (-1 = none) with
+  // conductances ew[...] and einv = 1 / d_f.
+  int64_t nC = 0;
+  std::vector<int32_t> fptr, fcol, enb;
+  std::vector<double> fcoef, ew, einv;
   int64_t nnz() const { return (int64_t)col.size(); }
 };
 
@@ -98,9 +106,11 @@ struct Hierarchy {
 // Device copy of one level.
 struct DevLevel {
   int n = 0, nnz = 0, nagg = 0;
+  int nC = 0;  // elimination level: kept rows (see HostLevel)
   int light_nnz = 0, nheavy = 0, nseg = 0;  // heavy rows live in their own CSR
   DBuf rowptr, col, w32, w64, deg32, deg64, sdinv32, sdinv64, agg, aggptr;
   DBuf heavy, hseg, hptr, hcol, hw32, hw64, seg_e, seg_row;
+  DBuf enb, ew32, ew64, einv32, einv64;  // eliminated rows
   bool unit = false;
   float omega32 = 0;
   double omega64 = 0;
@@ -108,6 +118,7 @@ struct DevLevel {
 
 struct DevHierarchy {
   std::vector<DevLevel> lv;
+  DevLevel fwd;  // forward operator of an elimination level 0 (rows = kept rows)
   DBuf cpinv;   // n_c x n_c FP64
   DBuf iperm;   // level-0 row -> graph node (int32)
   DBuf wgraph;  // level-0 original weights FP64 per nnz (for JL RHS), = w64 unless unit

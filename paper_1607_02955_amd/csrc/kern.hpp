@@ -37,6 +37,13 @@ struct LevelArgs {
   const int* seg_e = nullptr;  // [nseg+1] edge range of each segment
   const int* seg_row = nullptr;// [nseg] row of each segment
   void* hpart = nullptr;       // [nseg][W] partial sums (element type T)
+  // Elimination level (nC > 0): rows [nC, n) are eliminated; row nC + i has
+  // kept neighbours enb[2i], enb[2i+1] (-1 = none), conductances ew[2i..]
+  // and einv[i] = 1 / D_ii (element type T).
+  int nC = 0;
+  const int* enb = nullptr;
+  const void* ew = nullptr;
+  const void* einv = nullptr;
 };
 
 // Right-hand side of the FP64 residual kernel.
@@ -96,6 +103,17 @@ struct KernTable {
   // T[u] += x_u . s  (s = column sums, scal S_CS)
   void (*jl_rowdot)(int n, const double* x64, int ncols, const double* scal, double* T, hipStream_t);
   void (*zero)(void* p, size_t bytes, hipStream_t);
+  // Elimination level, forward step over the kept rows (lf = the forward
+  // operator, lf.n = kept rows): t = r + F r.  jac = 0 writes t to out;
+  // jac = 1 writes z = sd1 * t and partial sums of r . z (grid rows_grid).
+  void (*elim_fwd)(const LevelArgs& lf, const void* r, void* out, const void* sd1, double* part_rz,
+                   int jac, hipStream_t);
+  // Elimination level, back substitution z_f = (r_f + sum_c w_fc z_c) / D_ff
+  // for the eliminated rows, with partial sums of r . z over the eliminated
+  // rows (allrows = 0) or over all rows (allrows = 1); grid = elim_grid.
+  void (*elim_back)(const LevelArgs& l0, const void* r, void* z, double* part_rz, int allrows,
+                    hipStream_t);
+  int (*elim_grid)(int units);
   // tp[u] += node throughput of the block's unit flows ps[j] -> pt[j] (rows,
   // -1 = unused column) summed over its first ncols columns; seg_part holds
   // double[nseg] scratch for heavy rows.

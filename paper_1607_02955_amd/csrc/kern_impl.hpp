@@ -818,6 +818,110 @@ __global__ __launch_bounds__(kBlock) void k_jl_rowdot(int n, const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Elimination level (LAMG's elimination stage): with the kept rows C first
+// and the eliminated rows F an independent set, L = [L_CC L_CF; L_FC D_F]
+// and one exact block step of the preconditioner is
+//   forward  t_C = r_C - L_CF D_F^-1 r_F      (t_c = r_c + sum_f w_cf / d_f r_f)
+//   coarse   z_C = M_S^-1 t_C                  (M_S: the cycle on the Schur
+//                                               complement, the next level)
+//   back     z_F = D_F^-1 (r_F - L_FC z_C)     (z_f = (r_f + sum_c w_fc z_c) / d_f)
+// which is symmetric whenever M_S is.
+
+// t = r + F r over the kept rows (F = the forward operator); with JAC the
+// next level is smoothed once in place: out = sd1 * t, partial sums r . out.
+template <typename T, int W, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_elim_fwd(LevelArgs F, const T* __restrict__ r,
+                                                     T* __restrict__ out, const T* __restrict__ sd1,
+                                                     double* __restrict__ part) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[JAC ? RG * WS : 1];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  const T* w = static_cast<const T*>(F.w);
+  double acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = 0;
+  int tb, te;
+  block_tiles((F.n + RG - 1) / RG, rb, grb, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int u = t * RG + rg;
+    if (u >= F.n) continue;
+    T nb[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) nb[i] = 0;
+    gather_acc<T, W>(nb, F.col, w, F.rowptr[u], F.rowptr[u + 1], 0, 1,
+                     [&](int v) { return ld<T, V>(r + (size_t)v * W + c0); });
+    add_heavy<T, W>(F, u, nb, c0);
+    const size_t o = (size_t)u * W + c0;
+    const Vec<T, V> ru = ld<T, V>(r + o);
+    Vec<T, V> ov;
+    if constexpr (JAC) {
+      const T su = sd1[u];
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        ov.v[i] = su * (ru.v[i] + nb[i]);
+        acc[i] += double(ru.v[i]) * double(ov.v[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < V; ++i) ov.v[i] = ru.v[i] + nb[i];
+    }
+    st<T, V>(out + o, ov);
+  }
+  if constexpr (JAC) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+}
+
+// z_f for the eliminated rows, then partial sums of r . z over the eliminated
+// rows (ALL = false) or over every row (ALL = true).
+template <typename T, int W, bool ALL>
+__global__ __launch_bounds__(kBlock) void k_elim_back(LevelArgs L, const T* __restrict__ r,
+                                                      T* __restrict__ z, double* __restrict__ part) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[RG * WS];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  const T* ew = static_cast<const T*>(L.ew);
+  const T* einv = static_cast<const T*>(L.einv);
+  const int base = ALL ? 0 : L.nC;
+  double acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = 0;
+  int tb, te;
+  block_tiles((L.n - base + RG - 1) / RG, rb, grb, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int u = base + t * RG + rg;
+    if (u >= L.n) continue;
+    const size_t o = (size_t)u * W + c0;
+    const Vec<T, V> ru = ld<T, V>(r + o);
+    Vec<T, V> zu;
+    if (u >= L.nC) {
+      const int i = u - L.nC;
+      const int a = L.enb[2 * i], b = L.enb[2 * i + 1];
+      const T wa = ew[2 * i], di = einv[i];
+      const Vec<T, V> za = ld<T, V>(z + (size_t)a * W + c0);
+#pragma unroll
+      for (int k = 0; k < V; ++k) zu.v[k] = ru.v[k] + wa * za.v[k];
+      if (b >= 0) {
+        const T wb = ew[2 * i + 1];
+        const Vec<T, V> zb = ld<T, V>(z + (size_t)b * W + c0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) zu.v[k] += wb * zb.v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < V; ++k) zu.v[k] *= di;
+      st<T, V>(z + o, zu);
+    } else {
+      zu = ld<T, V>(z + o);
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] += double(ru.v[k]) * double(zu.v[k]);
+  }
+  block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+}
+
+// ---------------------------------------------------------------------------
 // Electrical currents of a block of unit s_j -> t_j flows (Sec. 2): column j
 // of the FP64 block x holds potentials with L x_j = e_{s_j} - e_{t_j}, so
 // edge {u, v} carries w_uv (x_u[j] - x_v[j]).  The throughput of node u in
@@ -1133,6 +1237,30 @@ struct Launch {
     if (!g) return;
     hipLaunchKernelGGL((k_jl_rowdot<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, scal, Tv);
   }
+  static int elim_grid(int units) { return std::min(grid_units(units, RG), kMaxGrid / 2); }
+  static void elim_fwd(const LevelArgs& L, const void* r, void* out, const void* sd1,
+                       double* part, int jac, hipStream_t s) {
+    heavy<HK_SPMM>(L, r, nullptr, nullptr, nullptr, s);
+    const int g = elim_grid(L.n);
+    if (!g) return;
+    if (jac)
+      hipLaunchKernelGGL((k_elim_fwd<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
+                         (T*)out, (const T*)sd1, part);
+    else
+      hipLaunchKernelGGL((k_elim_fwd<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
+                         (T*)out, (const T*)sd1, part);
+  }
+  static void elim_back(const LevelArgs& L, const void* r, void* z, double* part, int allrows,
+                        hipStream_t s) {
+    const int g = elim_grid(allrows ? L.n : L.n - L.nC);
+    if (!g) return;
+    if (allrows)
+      hipLaunchKernelGGL((k_elim_back<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
+                         (T*)z, part);
+    else
+      hipLaunchKernelGGL((k_elim_back<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
+                         (T*)z, part);
+  }
   static void throughput(const LevelArgs& L, const double* x64, int ncols, const int* ps,
                          const int* pt, double* seg_part, double* tp, hipStream_t s) {
     if (L.nseg) {
@@ -1173,6 +1301,9 @@ struct Launch {
     t.jl_rowdot = &jl_rowdot;
     t.zero = &zero;
     t.throughput = &throughput;
+    t.elim_fwd = &elim_fwd;
+    t.elim_back = &elim_back;
+    t.elim_grid = &elim_grid;
     t.edge_sq = &edge_sq;
     return t;
   }

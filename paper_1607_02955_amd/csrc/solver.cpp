@@ -25,12 +25,87 @@ namespace cfc {
 // device upload
 
 namespace {
+// Copies complete before returning, so the host vector may be a temporary.
 template <class T>
 void upload(Ctx* c, DBuf& d, const std::vector<T>& h, hipStream_t s) {
   d.alloc(c, h.size() * sizeof(T));
-  if (!h.empty()) CFC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (h.empty()) return;
+  CFC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  CFC_HIP(hipStreamSynchronize(s));
 }
 }  // namespace
+
+// Light CSR (rows of degree <= heavy_deg) plus heavy rows in their own CSR
+// cut into segments of heavy_deg edges, FP32 and FP64 weights.
+static void upload_csr(Ctx* c, DevLevel& d, int64_t n, const std::vector<int32_t>& rowptr,
+                       const std::vector<int32_t>& col, const std::vector<double>& w, bool unit,
+                       int heavy_deg, hipStream_t s) {
+  const int seg_len = heavy_deg;
+  std::vector<int32_t> lptr(n + 1, 0), lcol, hid(n, -1), hptr(1, 0), hcol, hseg(1, 0), seg_e(1, 0),
+      seg_row;
+  std::vector<double> lw, hw;
+  lcol.reserve(col.size());
+  lw.reserve(w.size());
+  d.nheavy = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    const int32_t e0 = rowptr[r], e1 = rowptr[r + 1];
+    if (e1 - e0 > heavy_deg) {
+      hid[r] = d.nheavy++;
+      for (int32_t e = e0; e < e1; ++e) {
+        hcol.push_back(col[e]);
+        hw.push_back(w[e]);
+        if ((int)(hcol.size() - hptr.back()) % seg_len == 0) seg_e.push_back((int32_t)hcol.size());
+      }
+      if (seg_e.back() != (int32_t)hcol.size()) seg_e.push_back((int32_t)hcol.size());
+      hptr.push_back((int32_t)hcol.size());
+      hseg.push_back((int32_t)seg_e.size() - 1);
+      seg_row.resize(seg_e.size() - 1, (int32_t)r);
+    } else {
+      for (int32_t e = e0; e < e1; ++e) {
+        lcol.push_back(col[e]);
+        lw.push_back(w[e]);
+      }
+    }
+    lptr[r + 1] = (int32_t)lcol.size();
+  }
+  d.light_nnz = (int)lcol.size();
+  d.nseg = (int)seg_e.size() - 1;
+  upload(c, d.rowptr, lptr, s);
+  upload(c, d.col, lcol, s);
+  if (!unit) {
+    std::vector<float> w32(lw.size()), hw32(hw.size());
+    for (size_t k = 0; k < lw.size(); ++k) w32[k] = (float)lw[k];
+    for (size_t k = 0; k < hw.size(); ++k) hw32[k] = (float)hw[k];
+    upload(c, d.w32, w32, s);
+    upload(c, d.w64, lw, s);
+    upload(c, d.hw32, hw32, s);
+    upload(c, d.hw64, hw, s);
+  }
+  if (d.nheavy) {
+    upload(c, d.heavy, hid, s);
+    upload(c, d.hseg, hseg, s);
+    upload(c, d.hptr, hptr, s);
+    upload(c, d.hcol, hcol, s);
+    upload(c, d.seg_e, seg_e, s);
+    upload(c, d.seg_row, seg_row, s);
+  }
+}
+
+template <class T>
+static std::vector<float> to_f32(const std::vector<T>& v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+  return o;
+}
+
+static uint64_t level_bytes(const DevLevel& d) {
+  uint64_t b = 0;
+  for (const DBuf* x : {&d.rowptr, &d.col, &d.w32, &d.w64, &d.deg32, &d.deg64, &d.sdinv32, &d.sdinv64,
+                        &d.agg, &d.aggptr, &d.heavy, &d.hseg, &d.hptr, &d.hcol, &d.hw32, &d.hw64,
+                        &d.seg_e, &d.seg_row, &d.enb, &d.ew32, &d.ew64, &d.einv32, &d.einv64})
+    b += x->bytes;
+  return b;
+}
 
 void upload_hierarchy(Graph& g) {
   Ctx* c = g.ctx;
@@ -45,7 +120,6 @@ void upload_hierarchy(Graph& g) {
     const char* e = std::getenv("CFC_HEAVY_DEG");
     return e ? std::max(16, std::atoi(e)) : 512;
   }();
-  const int seg_len = heavy_deg;
   for (int l = 0; l < L; ++l) {
     const HostLevel& h = H.lv[l];
     DevLevel& d = D->lv[l];
@@ -53,41 +127,9 @@ void upload_hierarchy(Graph& g) {
     d.nnz = (int)h.nnz();
     d.nagg = h.aggptr.empty() ? 0 : (int)h.aggptr.size() - 1;
     d.unit = (l == 0) && g.unit;
-    // light CSR (heavy rows keep no edges) + heavy CSR cut into segments
-    std::vector<int32_t> lptr(h.n + 1, 0), lcol, hid(h.n, -1), hptr(1, 0), hcol, hseg(1, 0), seg_e(1, 0),
-        seg_row;
-    std::vector<double> lw, hw;
-    lcol.reserve(h.col.size());
-    lw.reserve(h.w.size());
-    for (int64_t r = 0; r < h.n; ++r) {
-      const int32_t e0 = h.rowptr[r], e1 = h.rowptr[r + 1];
-      if (e1 - e0 > heavy_deg) {
-        hid[r] = d.nheavy++;
-        for (int32_t e = e0; e < e1; ++e) {
-          hcol.push_back(h.col[e]);
-          hw.push_back(h.w[e]);
-          if ((int)(hcol.size() - hptr.back()) % seg_len == 0) seg_e.push_back((int32_t)hcol.size());
-        }
-        if (seg_e.back() != (int32_t)hcol.size()) seg_e.push_back((int32_t)hcol.size());
-        hptr.push_back((int32_t)hcol.size());
-        hseg.push_back((int32_t)seg_e.size() - 1);
-        seg_row.resize(seg_e.size() - 1, (int32_t)r);
-      } else {
-        for (int32_t e = e0; e < e1; ++e) {
-          lcol.push_back(h.col[e]);
-          lw.push_back(h.w[e]);
-        }
-      }
-      lptr[r + 1] = (int32_t)lcol.size();
-    }
-    d.light_nnz = (int)lcol.size();
-    d.nseg = (int)seg_e.size() - 1;
-    upload(c, d.rowptr, lptr, s);
-    upload(c, d.col, lcol, s);
-    std::vector<float> w32(lw.size()), deg32(h.n), sd32(h.n), hw32(hw.size());
+    upload_csr(c, d, h.n, h.rowptr, h.col, h.w, d.unit, heavy_deg, s);
+    std::vector<float> deg32(h.n), sd32(h.n);
     std::vector<double> sd64(h.n);
-    for (size_t k = 0; k < lw.size(); ++k) w32[k] = (float)lw[k];
-    for (size_t k = 0; k < hw.size(); ++k) hw32[k] = (float)hw[k];
     for (int64_t r = 0; r < h.n; ++r) {
       // FP32 diagonal = FP32 sum of the FP32 off-diagonals, so that the FP32
       // operator keeps its row sums (L 1 = 0) as closely as FP32 allows.
@@ -97,20 +139,6 @@ void upload_hierarchy(Graph& g) {
       sd32[r] = sacc > 0 ? (float)(H.omega / (double)sacc) : 0.f;
       sd64[r] = h.deg[r] > 0 ? H.omega / h.deg[r] : 0.0;
     }
-    if (!d.unit) {
-      upload(c, d.w32, w32, s);
-      upload(c, d.w64, lw, s);
-      upload(c, d.hw32, hw32, s);
-      upload(c, d.hw64, hw, s);
-    }
-    if (d.nheavy) {
-      upload(c, d.heavy, hid, s);
-      upload(c, d.hseg, hseg, s);
-      upload(c, d.hptr, hptr, s);
-      upload(c, d.hcol, hcol, s);
-      upload(c, d.seg_e, seg_e, s);
-      upload(c, d.seg_row, seg_row, s);
-    }
     upload(c, d.deg32, deg32, s);
     upload(c, d.deg64, h.deg, s);
     upload(c, d.sdinv32, sd32, s);
@@ -119,11 +147,22 @@ void upload_hierarchy(Graph& g) {
       upload(c, d.agg, h.agg, s);
       upload(c, d.aggptr, h.aggptr, s);
     }
+    if (h.nC > 0) {
+      // elimination level: forward operator (kept rows x eliminated rows;
+      // hubs with many eliminated neighbours go to short heavy segments)
+      d.nC = (int)h.nC;
+      upload_csr(c, D->fwd, h.nC, h.fptr, h.fcol, h.fcoef, false, 64, s);
+      D->fwd.n = (int)h.nC;
+      D->fwd.nnz = (int)h.fcol.size();
+      upload(c, d.enb, h.enb, s);
+      upload(c, d.ew64, h.ew, s);
+      upload(c, d.ew32, to_f32(h.ew), s);
+      upload(c, d.einv64, h.einv, s);
+      upload(c, d.einv32, to_f32(h.einv), s);
+      D->bytes += level_bytes(D->fwd);
+    }
     d.omega64 = H.omega;
-    for (const DBuf* b : {&d.rowptr, &d.col, &d.w32, &d.w64, &d.deg32, &d.deg64, &d.sdinv32, &d.sdinv64,
-                          &d.agg, &d.aggptr, &d.heavy, &d.hseg, &d.hptr, &d.hcol, &d.hw32, &d.hw64, &d.seg_e,
-                          &d.seg_row})
-      D->bytes += b->bytes;
+    D->bytes += level_bytes(d);
   }
   // coarsest pseudoinverse, zero-padded to a multiple of 16
   const int nc = (int)H.lv[L - 1].n;
@@ -178,6 +217,35 @@ static LevelArgs level_args(const Graph& g, int l, bool fp64) {
     a.seg_e = d.seg_e.as<int>();
     a.seg_row = d.seg_row.as<int>();
   }
+  if (d.nC > 0) {
+    a.nC = d.nC;
+    a.enb = d.enb.as<int>();
+    a.ew = fp64 ? d.ew64.p : d.ew32.p;
+    a.einv = fp64 ? d.einv64.p : d.einv32.p;
+  }
+  return a;
+}
+
+// The forward operator of an elimination level 0 (kept rows x all rows).
+static LevelArgs fwd_args(const Graph& g, bool fp64) {
+  const DevLevel& d = g.D->fwd;
+  LevelArgs a;
+  a.n = d.n;
+  a.rowptr = d.rowptr.as<int>();
+  a.col = d.col.as<int>();
+  a.w = fp64 ? (const void*)d.w64.p : (const void*)d.w32.p;
+  a.split = 1;
+  a.nheavy = d.nheavy;
+  a.nseg = d.nseg;
+  if (d.nheavy) {
+    a.heavy = d.heavy.as<int>();
+    a.hseg = d.hseg.as<int>();
+    a.hptr = d.hptr.as<int>();
+    a.hcol = d.hcol.as<int>();
+    a.hw = fp64 ? (const void*)d.hw64.p : (const void*)d.hw32.p;
+    a.seg_e = d.seg_e.as<int>();
+    a.seg_row = d.seg_row.as<int>();
+  }
   return a;
 }
 
@@ -209,6 +277,13 @@ Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem) {
       w.la[l].hpart = w.hpart[l].p;
       if (l == 0) w.la64.hpart = w.hpart[0].p;
     }
+  if (g.D->lv[0].nC > 0) {
+    w.lf = fwd_args(g, fp64);
+    if (g.D->fwd.nseg) {
+      w.fpart.alloc(c, (size_t)g.D->fwd.nseg * W * 8);
+      w.lf.hpart = w.fpart.p;
+    }
+  }
   const size_t es = fp64 ? 8 : 4;
   const size_t n0 = (size_t)g.D->lv[0].n;
   const size_t blk = n0 * W * es;
@@ -217,7 +292,8 @@ Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem) {
   w.xl.resize(L);
   for (int l = 1; l < L; ++l) {
     w.b[l].alloc(c, (size_t)g.D->lv[l].n * W * es);
-    w.xl[l].alloc(c, (size_t)g.D->lv[l].n * W * es);
+    // below an elimination level the kept rows of z hold level 1's iterate
+    if (l > 1 || g.D->lv[0].nC == 0) w.xl[l].alloc(c, (size_t)g.D->lv[l].n * W * es);
   }
   w.x64.alloc(c, n0 * W * 8);
   w.pairs.alloc(c, 2 * W * sizeof(int) + 2 * (W + 1) * sizeof(int));
@@ -274,6 +350,10 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     g_rz = grid_for(d0.n, k.rg);
     return;
   }
+  if (d0.nC > 0 && L >= 2) {
+    vcycle_elim(update, first_x, r_in, r_out);
+    return;
+  }
   if (L == 1) {  // single-level hierarchy: the preconditioner is L^+ itself
     if (update) {
       LevelArgs a = w.la[0];
@@ -324,6 +404,70 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   prof_end(K_PROLONG0, pb);
   g_rz = k.rows_grid(w.la[0], d0.n);
   bytes += pb;
+}
+
+// V-cycle whose level 0 is an elimination level: the CG update on all rows,
+// the forward step onto the kept rows (level 1's rows), the cycle from level
+// 1 with its iterate in the kept rows of z, and the back substitution.
+void Solver::vcycle_elim(bool update, bool first_x, const void* r_in, void* r_out) {
+  Workspace& w = *ws;
+  const KernTable& k = *w.kt;
+  hipStream_t s = stream;
+  const int L = nuse;
+  const bool exact = nuse == w.nlev;
+  const size_t es = w.fp64 ? 8 : 4;
+  const double nw = (double)w.W * es;
+  const DevLevel& d0 = g->D->lv[0];
+  const DevLevel& fw = g->D->fwd;
+  const int n = d0.n, nc = d0.nC;
+  const void* rsrc = update ? r_out : r_in;
+  if (update) {
+    prof_begin(K_RESTRICT0);
+    LevelArgs a = w.la[0];
+    a.nagg = 0;
+    k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x, 1,
+                      w.part_ptr(P_RR), w.part_ptr(P_CS), s);
+    const double ub = n * nw * (first_x ? 5 : 6);
+    prof_end(K_RESTRICT0, ub);
+    bytes += ub;
+    g_rr = g_cs = k.rows_grid(a, n);
+  }
+  const double fb = 2.0 * nc * nw + (double)(n - nc) * nw + 8.0 * fw.nnz + 4.0 * nc;
+  const double bb = (double)(n - nc) * nw * 2 + 2.0 * (n - nc) * nw + 16.0 * (n - nc);
+  if (L == 2 && !exact) {
+    // Schur complement smoothed once: z_C = S t_C, fused into the forward step
+    k.elim_fwd(w.lf, rsrc, w.z.p, w.la[1].sd, w.part_ptr(P_RZ), 1, s);
+    const int g1 = k.elim_grid(nc);
+    k.elim_back(w.la[0], rsrc, w.z.p, w.part_ptr(P_RZ) + (size_t)g1 * w.W, 0, s);
+    g_rz = g1 + k.elim_grid(n - nc);
+    bytes += fb + bb;
+    return;
+  }
+  k.elim_fwd(w.lf, rsrc, w.b[1].p, nullptr, nullptr, 0, s);
+  bytes += fb;
+  auto xl = [&](int l) { return l == 1 ? w.z.p : w.xl[l].p; };
+  for (int l = 1; l + 1 < L; ++l) {
+    const DevLevel& d = g->D->lv[l];
+    k.restrict_(w.la[l], w.b[l].p, w.b[l + 1].p, s);
+    bytes += d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * (d.nagg + 1);
+  }
+  if (exact) {
+    const int ncs = g->D->nc;
+    k.coarse(ncs, (ncs + 15) / 16 * 16, g->D->cpinv.as<double>(), w.b[L - 1].p, xl(L - 1), s);
+    bytes += 2.0 * ncs * nw + 8.0 * ncs * ncs;
+  } else {
+    const DevLevel& d = g->D->lv[L - 1];
+    k.jacobi(w.la[L - 1], w.b[L - 1].p, xl(L - 1), nullptr, s);
+    bytes += 2.0 * d.n * nw + es * d.n;
+  }
+  for (int l = L - 2; l >= 1; --l) {
+    const DevLevel& d = g->D->lv[l];
+    k.prolong_smooth(w.la[l], w.b[l].p, xl(l + 1), xl(l), nullptr, s);
+    bytes += 2.0 * d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * d.n;
+  }
+  k.elim_back(w.la[0], rsrc, w.z.p, w.part_ptr(P_RZ), 1, s);
+  g_rz = k.elim_grid(n);
+  bytes += bb + 2.0 * nc * nw;
 }
 
 void Solver::prof_begin(int which) {

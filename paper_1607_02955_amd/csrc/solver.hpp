@@ -21,6 +21,8 @@ struct Workspace {
   DBuf x, ra, rb, p, q, z;    // level 0, inner element type
   std::vector<DBuf> b, xl;    // levels >= 1: right-hand side and iterate
   std::vector<DBuf> hpart;    // per level: heavy-row segment partials
+  LevelArgs lf;               // forward operator of an elimination level 0
+  DBuf fpart;                 // its heavy-row segment partials
   DBuf x64;                   // FP64 solution block
   DBuf rhs;                   // FP64 dense right-hand sides (on demand)
   DBuf pairs;                 // int32 ps[W], pt[W], segment bounds
@@ -71,6 +73,7 @@ struct Solver {
   void iteration(bool first, void* r_in, void* r_out);
   void capture_pair();
   void vcycle(bool update, bool first_x, const void* r_in, void* r_out);
+  void vcycle_elim(bool update, bool first_x, const void* r_in, void* r_out);
   int pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
   void solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& p, int32_t* status,
                    double* final_rel);

@@ -254,3 +254,67 @@ def test_edge_cases(ctx):
         g2.solve(np.array([1.0, 0.0]))  # does not sum to zero
     with pytest.raises(cfc.CfcError, match="STATE"):
         g2.farness_jl([0])
+
+
+def leafy_graph(seed=31, n=3000):
+    """Weighted random graph with many degree-1 and degree-2 nodes (pendant
+    trees and chains hung on a core), like the low-degree fringe of
+    skewed-degree networks."""
+    core = synth.random_connected(n // 2, 3 * n // 2, seed=seed)
+    rng = np.random.default_rng(seed)
+    a, b, w = [core.u], [core.v], [core.w]
+    nxt = core.n
+    for _ in range(n // 2):
+        kind = rng.integers(0, 3)
+        anchor = int(rng.integers(0, nxt))
+        if kind == 0:    # leaf
+            a.append([anchor]); b.append([nxt]); nxt += 1
+        elif kind == 1:  # chain of two
+            a.append([anchor, nxt]); b.append([nxt, nxt + 1]); nxt += 2
+        else:            # degree-2 bridge between two core nodes
+            other = int(rng.integers(0, core.n))
+            if other == anchor:
+                continue
+            a.append([anchor, nxt]); b.append([nxt, other]); nxt += 1
+        w.append(rng.uniform(1, 4, len(a[-1])))
+    a, b, w = np.concatenate(a), np.concatenate(b), np.concatenate(w)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    key, first = np.unique(lo * nxt + hi, return_index=True)
+    return synth.EdgeList(nxt, key // nxt, key % nxt, w[first])
+
+
+@pytest.mark.parametrize("W,prec", [(64, 0), (256, 1), (32, 0)])
+def test_elimination_level_all_depths(ctx, W, prec):
+    """An elimination level (exact Schur complement of an independent set of
+    degree-1/2 nodes) in front of the aggregation levels: every V-cycle depth
+    and the full exact path give the oracle's resistances."""
+    eg = leafy_graph(seed=W)
+    say("elimination", W, prec, eg.n, eg.m)
+    g = load(ctx, eg, coarsest_max=64, eliminate=2)
+    info = g.info()
+    assert info["eliminated"] > eg.n // 10 and info["levels"] >= 4
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(W)
+    s = rng.integers(0, eg.n, 2 * W + 5)
+    t = rng.integers(0, eg.n, 2 * W + 5)
+    tol = 1e-8 if prec == 0 else 1e-10
+    for depth in (1, 2, 3, 0):
+        r, st = g.resistance(s, t, block=W, precision=prec, tol=tol, levels=depth, stats=True,
+                             max_inner=3000)
+        say("  depth", depth, st["inner_iters"], st["levels_used"])
+        np.testing.assert_allclose(r, Rm[s, t], rtol=10 * tol, atol=1e-12)
+    r_g = g.resistance(s, t, block=W, precision=prec, tol=tol, levels=2, use_graph=1, max_inner=3000)
+    np.testing.assert_allclose(r_g, Rm[s, t], rtol=10 * tol, atol=1e-12)
+
+
+def test_elimination_to_two_nodes_is_exact(ctx):
+    """A star loses every leaf but one: the elimination level over a two-node
+    coarsest level is an exact solver."""
+    eg = synth.star_graph(1500)
+    g = load(ctx, eg, coarsest_max=64, eliminate=1)
+    assert g.info()["level_n"] == [1500, 2]
+    s = np.arange(1, 200)
+    t = np.arange(2, 201) % 1500
+    r, st = g.resistance(s, t, block=256, precision=1, tol=1e-12, stats=True)
+    np.testing.assert_allclose(r, np.where(s == t, 0.0, 2.0), rtol=1e-12)
+    assert st["inner_iters"] <= 3 * st["blocks"]

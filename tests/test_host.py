@@ -91,17 +91,45 @@ def _level_laplacian(lv):
     return L
 
 
+def _check_elimination_level(lv, nxt):
+    """Kept rows first; eliminated rows form an independent set of degree 1
+    or 2; the next level is the Schur complement on the kept rows."""
+    n, nc = lv["n"], lv["n_coarse"]
+    assert l_ok(nc, n) and nxt["n"] == nc
+    Lf = _level_laplacian(lv)
+    F = np.arange(nc, n)
+    LFF = Lf[np.ix_(F, F)]
+    np.testing.assert_allclose(LFF, np.diag(np.diag(LFF)), atol=0)  # independent set
+    deg = np.diff(lv["row_ptr"])[F]
+    assert deg.min() >= 1 and deg.max() <= 2
+    nb = lv["elim_nb"].reshape(-1, 2)
+    for i, r in enumerate(F):
+        got = sorted(x for x in nb[i] if x >= 0)
+        assert got == sorted(lv["col"][lv["row_ptr"][r]:lv["row_ptr"][r + 1]].tolist())
+        assert max(got) < nc
+    C = np.arange(nc)
+    S = Lf[np.ix_(C, C)] - Lf[np.ix_(C, F)] @ np.linalg.solve(LFF, Lf[np.ix_(F, C)])
+    Lc = _level_laplacian(nxt)
+    np.testing.assert_allclose(S, Lc, atol=1e-11 * max(1.0, np.abs(Lc).max()))
+
+
+def l_ok(nc, n):
+    return 2 <= nc < n
+
+
 @pytest.mark.parametrize("maker", [
     lambda: synth.grid(40),
     lambda: synth.barabasi_albert(3000, 4, seed=2),
     lambda: synth.rmat(11, seed=3),
     lambda: synth.road_grid(48, seed=4),
     lambda: synth.star_graph(2000),
+    lambda: synth.random_connected(1500, 2200, seed=9),
 ])
-def test_hierarchy_invariants(hctx, maker):
+@pytest.mark.parametrize("elim", [0, 2])
+def test_hierarchy_invariants(hctx, maker, elim):
     eg = maker()
     g = cfc.Graph.from_edgelist(hctx, eg)
-    g.build_hierarchy(coarsest_max=128)
+    g.build_hierarchy(coarsest_max=128, eliminate=elim)
     info = g.info()
     L = info["levels"]
     assert L >= 2 and info["level_n"][-1] <= 128
@@ -116,6 +144,9 @@ def test_hierarchy_invariants(hctx, maker):
     for l in range(L - 1):
         lv = g.level(l)
         nxt = g.level(l + 1)
+        if lv["elimination"]:
+            _check_elimination_level(lv, nxt)
+            continue
         agg, ap = lv["agg"], lv["agg_ptr"]
         assert ap[0] == 0 and ap[-1] == lv["n"] and np.all(np.diff(ap) >= 1)
         assert np.all(np.diff(agg) >= 0), "aggregates must be contiguous row ranges"
