@@ -71,14 +71,21 @@ def make_workload(name):
         g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
         return g, dict(kind="jl", k=512, block=512, tol=1e-6, queries=100)
     if name == "grid32_exact":
+        # exact farness and closeness of node 0 (a corner): 1023 solves
         g = synth.grid(32)
-        return g, dict(kind="exact", block=256, tol=1e-10, queries=1, precision=1)
+        return g, dict(kind="exact", block=256, tol=1e-10, queries=1, precision=1, nodes=[0])
     if name == "rmat20_sampling":
         g = synth.cached("rmat20", synth.rmat, 20, 16, seed=1)
         return g, dict(kind="sampling", k=1000, block=256, tol=1e-6, queries=64)
     if name == "road2048_jl256":
         g = synth.cached("road2048", synth.road_grid, 2048, seed=1)
         return g, dict(kind="jl", k=256, block=0, tol=1e-6, queries=32)
+    if name == "road2048_jl256_sampling500":
+        # the road workload as a whole: projection k = 256 plus Sampling with
+        # 500 pivots for 32 query nodes (16,256 right-hand sides)
+        g = synth.cached("road2048", synth.road_grid, 2048, seed=1)
+        return g, dict(kind="jl+sampling", k=256, k_sampling=500, block=0, tol=1e-6, queries=32,
+                       use_graph=1)
     if name == "ba100k_shared1000":
         # one shared set of 1000 pivots for 100 query nodes: 1099 solves
         g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
@@ -216,7 +223,7 @@ def cpu_baseline(eg, spec, budget_s=20.0):
             return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",
                     "sample": f"{done} random source/sink pairs: oracle Jacobi-PCG (FP64) to rel. "
                               f"residual {spec['tol']:g} plus node throughput, {dt:.1f} s"}
-        if spec["kind"] in ("jl", "spanning_jl"):
+        if spec["kind"] in ("jl", "spanning_jl", "jl+sampling"):
             Y = E.projection_rhs(eg, spec["k"], seed=1)
             cols = 1
             t0 = time.perf_counter()
@@ -258,6 +265,8 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--levels", type=int, default=0, help="V-cycle depth (0 = autotuned)")
+    ap.add_argument("--eliminate", type=int, default=1,
+                    help="low-degree elimination level: 0 off, 1 when >= 5%% of nodes qualify, 2 always")
     ap.add_argument("--block", type=int, default=-1, help="block width W (default: the workload's)")
     ap.add_argument("--use-graph", type=int, default=-1,
                     help="replay PCG iterations from a HIP graph (1/0; default: on for n < 100000)")
@@ -297,12 +306,12 @@ def main():
     ctx = cfc.Context(0)
     g = cfc.Graph.from_edgelist(ctx, eg)
     t0 = time.perf_counter()
-    g.build_hierarchy()
+    g.build_hierarchy(eliminate=args.eliminate)
     setup_s = time.perf_counter() - t0
     info = g.info()
-    nodes = synth.query_nodes(eg.n, spec["queries"], seed=1)
+    nodes = np.array(spec["nodes"], np.int64) if "nodes" in spec else synth.query_nodes(eg.n, spec["queries"], seed=1)
     prec = spec.get("precision", 0)
-    use_graph = args.use_graph if args.use_graph >= 0 else int(eg.n < 100000)
+    use_graph = args.use_graph if args.use_graph >= 0 else spec.get("use_graph", int(eg.n < 100000))
     if args.block >= 0:
         spec["block"] = args.block
     kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels,
@@ -316,6 +325,17 @@ def main():
             return st, spec["k"]
         if spec["kind"] == "sampling":
             _, _, st = g.farness_sampling(nodes, spec["k"], seed=seed, stats=True, **kw2)
+            return st, st["columns"]
+        if spec["kind"] == "jl+sampling":
+            st = g.jl_sketch(spec["k"], seed=seed, stats=True, **kw2)
+            g.farness_jl(nodes)
+            _, _, st2 = g.farness_sampling(nodes, spec["k_sampling"], seed=seed, stats=True, **kw2)
+            for f in ("columns", "converged", "inner_iters", "refine_steps", "blocks", "model_bytes",
+                      "solve_ms"):
+                st[f] += st2[f]
+            for f in ("kernel_ms", "kernel_bytes", "kernel_launches"):
+                st[f] = [a + b for a, b in zip(st[f], st2[f])]
+            st["max_rel_residual"] = max(st["max_rel_residual"], st2["max_rel_residual"])
             return st, st["columns"]
         if spec["kind"] == "shared":
             _, _, st = g.farness_sampling_shared(nodes, spec["k"], seed=seed, stats=True, **kw2)
@@ -374,6 +394,7 @@ def main():
                    "estimator": spec["kind"], "k": spec.get("k"), "block_width": agg["W"],
                    "vcycle_depth": agg.get("depth"), "hip_graph": bool(use_graph),
                    "tol": spec["tol"], "query_nodes": spec["queries"], "levels": info["levels"],
+                   "eliminated_nodes": info["eliminated"],
                    "operator_complexity": round(info["operator_complexity"], 3)},
         "roofline": roof,
         "solve": {"pcg_iters_per_step": agg["iters"] / args.steps,
