@@ -302,13 +302,18 @@ def main():
     import paper_1607_02955_amd as cfc
     import synth
 
+    def progress(msg):
+        print(f"# {msg}", file=sys.stderr, flush=True)
+
     eg, spec = make_workload(args.workload)
+    progress(f"graph {eg.name}: n={eg.n} m={eg.m}")
     ctx = cfc.Context(0)
     g = cfc.Graph.from_edgelist(ctx, eg)
     t0 = time.perf_counter()
     g.build_hierarchy(eliminate=args.eliminate)
     setup_s = time.perf_counter() - t0
     info = g.info()
+    progress(f"hierarchy: {info['levels']} levels, {info['eliminated']} eliminated, {setup_s:.1f} s")
     nodes = np.array(spec["nodes"], np.int64) if "nodes" in spec else synth.query_nodes(eg.n, spec["queries"], seed=1)
     prec = spec.get("precision", 0)
     use_graph = args.use_graph if args.use_graph >= 0 else spec.get("use_graph", int(eg.n < 100000))
@@ -329,6 +334,7 @@ def main():
         if spec["kind"] == "jl+sampling":
             st = g.jl_sketch(spec["k"], seed=seed, stats=True, **kw2)
             g.farness_jl(nodes)
+            progress(f"  projection part: {spec['k']} columns")
             _, _, st2 = g.farness_sampling(nodes, spec["k_sampling"], seed=seed, stats=True, **kw2)
             for f in ("columns", "converged", "inner_iters", "refine_steps", "blocks", "model_bytes",
                       "solve_ms"):
@@ -351,6 +357,7 @@ def main():
 
     for i in range(args.warmup):
         step(1000 + i)
+        progress(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     agg = {"cols": 0, "iters": 0, "refine": 0, "bytes": 0.0, "kms": [0.0] * 3, "kbytes": [0.0] * 3,
            "kl": [0] * 3, "solve_ms": 0.0, "maxrel": 0.0, "W": 0}
@@ -369,6 +376,7 @@ def main():
         agg["maxrel"] = max(agg["maxrel"], st["max_rel_residual"])
         agg["W"] = st["block_width"]
         agg["depth"] = st["levels_used"]
+        progress(f"step {i + 1}/{args.steps}: {cols} columns")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = agg["cols"] / dt
@@ -405,6 +413,7 @@ def main():
                   "setup_s": round(setup_s, 3)},
     }
     if not args.no_full_depth and info["levels"] > 1 and agg["depth"] != info["levels"]:
+        progress("full-depth comparison")
         # the same workload through the full multigrid depth, for comparison
         step(2000, levels=info["levels"])
         torch.cuda.synchronize()
@@ -415,7 +424,9 @@ def main():
         torch.cuda.synchronize()
         out["full_depth_multigrid"] = {"value": round(cols / (time.perf_counter() - t1), 2),
                                        "unit": "solved RHS/s", "vcycle_depth": info["levels"]}
+    progress(f"timed: {value:.1f} RHS/s")
     if not args.no_fp64_baseline:
+        progress("plain FP64 one-right-hand-side GPU solve")
         # the plain FP64 one-right-hand-side-at-a-time GPU solve on the same
         # hierarchy: 8 pair right-hand sides
         rng = np.random.default_rng(5)
@@ -431,6 +442,7 @@ def main():
                                    "pcg_iters_per_rhs": st1["inner_iters"] / 8,
                                    "speedup_of_batched": round(value / (8 / d1), 2)}
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(eg, spec, args.cpu_budget)
         out["cpu_baseline"]["host"] = os.uname().nodename
     print(json.dumps(out), flush=True)
