@@ -121,7 +121,11 @@ typedef struct {
                             aggregating.  0 = off, 1 = when it removes at
                             least 5% of the nodes (default), 2 = whenever
                             any node qualifies */
-  int32_t pad;
+  int32_t device;        /* 1 = run the affinity, Galerkin and renumbering
+                            steps on the context's GPU (default; the result
+                            is bit-identical to the host build), 0 = host
+                            only.  Host-only contexts always build on the
+                            host. */
 } cfc_setup_params;
 
 typedef struct {

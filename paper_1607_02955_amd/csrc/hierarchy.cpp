@@ -31,10 +31,13 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "internal.hpp"
 #include "rng.hpp"
+#include "setup.hpp"
 
 namespace cfc {
 
@@ -48,22 +51,11 @@ cfc_setup_params default_setup() {
   p.mu = 1.5;
   p.seed = 1;
   p.eliminate = 1;
-  p.pad = 0;
+  p.device = 1;
   return p;
 }
 
 namespace {
-
-struct BLevel {  // a level in build numbering
-  int64_t n = 0;
-  std::vector<int32_t> rowptr, col;
-  std::vector<double> w, deg;
-  std::vector<int32_t> agg;  // to next level (build numbering)
-  int64_t nagg = 0;
-  // elimination level: cidx[u] = u's node on the next level, -1 if eliminated
-  std::vector<int32_t> cidx;
-  std::vector<int32_t> F;    // eliminated nodes
-};
 
 // Choose an independent set of degree-1 nodes, then degree-2 nodes (in id
 // order), and form the Schur complement graph on the rest.  Returns false
@@ -130,10 +122,13 @@ bool eliminate(BLevel& B, int mode, BLevel& R) {
   return true;
 }
 
-constexpr uint64_t kTagTestVec = 0x5456ull;
+}  // namespace
 
-// Affinity-based greedy aggregation.  Returns the number of aggregates.
-int64_t aggregate(const BLevel& L, int level, const cfc_setup_params& p, std::vector<int32_t>& agg) {
+// Affinity of every CSR entry e = (u, col[e]) of a level, times
+// (1 + 1e-12 w_e) so that exact ties go to the heavier edge.  The device
+// version (setup_dev.hip) performs the same FP64 operations in the same
+// order, without contraction, and returns identical values.
+std::vector<double> affinities(const BLevel& L, int level, const cfc_setup_params& p) {
   const int64_t n = L.n;
   const int K = std::max(1, p.test_vectors);
   // test vectors, node-major n x K
@@ -176,6 +171,20 @@ int64_t aggregate(const BLevel& L, int level, const cfc_setup_params& p, std::ve
     double den = nx[u] * nx[v];
     return den > 0 ? s * s / den : 0.0;
   };
+  std::vector<double> aff(L.col.size());
+  for (int64_t u = 0; u < n; ++u)
+    for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e)
+      aff[e] = affinity(u, L.col[e]) * (1.0 + 1e-12 * L.w[e]);
+  return aff;
+}
+
+namespace {
+
+// Greedy aggregation in ascending-degree order over precomputed affinities.
+// Returns the number of aggregates.
+int64_t aggregate(const BLevel& L, const std::vector<double>& aff, const cfc_setup_params& p,
+                  std::vector<int32_t>& agg) {
+  const int64_t n = L.n;
   std::vector<int64_t> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
@@ -191,7 +200,7 @@ int64_t aggregate(const BLevel& L, int level, const cfc_setup_params& p, std::ve
     double bv = -1, sv = -1;
     for (int32_t e = L.rowptr[u]; e < L.rowptr[u + 1]; ++e) {
       int64_t v = L.col[e];
-      double a = affinity(u, v) * (1.0 + 1e-12 * L.w[e]);
+      const double a = aff[e];
       if (a > sv) { sv = a; strongest = v; }
       if (agg[v] >= 0 && size[agg[v]] >= cap) continue;
       if (a > bv) { bv = a; best = v; }
@@ -409,12 +418,35 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
     BLevel R;
     if (B[0].n > p.coarsest_max && eliminate(B[0], p.eliminate, R)) B.push_back(std::move(R));
   }
+  if (p.device != 0 && p.device != 1) fail(CFC_E_INVALID, "device must be 0 or 1");
+  std::unique_ptr<DeviceSetup> dev;
+  std::vector<int> dh;  // device handle of each build level
+  if (p.device && !g.ctx->host_only()) {
+    dev = std::make_unique<DeviceSetup>(g.ctx);
+    for (const BLevel& b : B) dh.push_back(dev->add(b));
+  }
+  const bool trace = std::getenv("CFC_DEBUG") != nullptr;
+  auto ms_since = [](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+  };
   while (B.back().n > p.coarsest_max && (int)B.size() < CFC_MAX_LEVELS) {
     BLevel& F = B.back();
     std::vector<int32_t> agg;
-    int64_t nc = aggregate(F, (int)B.size() - 1, p, agg);
+    auto ta = std::chrono::steady_clock::now();
+    const int lvl = (int)B.size() - 1;
+    const std::vector<double> aff = dev ? dev->affinities(dh[lvl], lvl, p) : affinities(F, lvl, p);
+    int64_t nc = aggregate(F, aff, p, agg);
+    const double t_agg = ms_since(ta);
     if (nc >= F.n) break;  // no progress (cannot happen on a connected graph with n >= 2)
-    BLevel C = galerkin(F, agg, nc);
+    ta = std::chrono::steady_clock::now();
+    BLevel C;
+    if (dev)
+      dh.push_back(dev->galerkin(dh[lvl], agg, nc, C));
+    else
+      C = galerkin(F, agg, nc);
+    if (trace)
+      std::fprintf(stderr, "[cfc] setup level %d: n %lld nnz %zu -> %lld: aggregate %.0f ms, galerkin %.0f ms\n",
+                   (int)B.size() - 1, (long long)F.n, F.col.size(), (long long)nc, t_agg, ms_since(ta));
     F.agg = std::move(agg);
     F.nagg = nc;
     B.push_back(std::move(C));
@@ -424,6 +456,7 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   // Locality keys: level-0 nodes get their position in a Cuthill-McKee
   // (breadth-first, ascending degree) sweep from a pseudo-peripheral node; a
   // coarse node gets the smallest key of its aggregate.
+  auto tk = std::chrono::steady_clock::now();
   std::vector<std::vector<int64_t>> key(L);
   key[0] = bfs_keys(B[0]);
   for (int l = 0; l + 1 < L; ++l) {
@@ -489,15 +522,24 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
     O.col.reserve(F.col.size());
     O.w.reserve(F.w.size());
     O.deg.resize(F.n);
-    std::vector<std::pair<int32_t, double>> row;
-    for (int64_t r = 0; r < F.n; ++r) {
-      int32_t old = order[l][r];
-      row.clear();
-      for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e) row.emplace_back(newid[l][F.col[e]], F.w[e]);
-      std::sort(row.begin(), row.end());
-      for (auto& x : row) { O.col.push_back(x.first); O.w.push_back(x.second); }
-      O.rowptr[r + 1] = (int32_t)O.col.size();
-      O.deg[r] = F.deg[old];
+    if (dev) {
+      dev->renumber(dh[l], newid[l], O.col, O.w);
+      for (int64_t r = 0; r < F.n; ++r) {
+        const int32_t old = order[l][r];
+        O.rowptr[r + 1] = O.rowptr[r] + (F.rowptr[old + 1] - F.rowptr[old]);
+        O.deg[r] = F.deg[old];
+      }
+    } else {
+      std::vector<std::pair<int32_t, double>> row;
+      for (int64_t r = 0; r < F.n; ++r) {
+        int32_t old = order[l][r];
+        row.clear();
+        for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e) row.emplace_back(newid[l][F.col[e]], F.w[e]);
+        std::sort(row.begin(), row.end());
+        for (auto& x : row) { O.col.push_back(x.first); O.w.push_back(x.second); }
+        O.rowptr[r + 1] = (int32_t)O.col.size();
+        O.deg[r] = F.deg[old];
+      }
     }
     if (!F.cidx.empty()) {
       // forward operator over kept rows and the eliminated rows' neighbours
@@ -542,6 +584,7 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
         if (O.agg[r] < O.agg[r - 1]) fail(CFC_E_INTERNAL, "aggregates are not contiguous");
     }
   }
+  if (trace) std::fprintf(stderr, "[cfc] setup ordering + level copies %.0f ms\n", ms_since(tk));
   // coarsest pseudoinverse in final numbering
   {
     BLevel C;

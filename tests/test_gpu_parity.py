@@ -318,3 +318,40 @@ def test_elimination_to_two_nodes_is_exact(ctx):
     r, st = g.resistance(s, t, block=256, precision=1, tol=1e-12, stats=True)
     np.testing.assert_allclose(r, np.where(s == t, 0.0, 2.0), rtol=1e-12)
     assert st["inner_iters"] <= 3 * st["blocks"]
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: synth.grid(60),
+    lambda: synth.barabasi_albert(6000, 4, seed=3),
+    lambda: synth.rmat(13, seed=5),
+    lambda: synth.road_grid(70, seed=6),
+    lambda: leafy_graph(seed=9),
+    lambda: synth.star_graph(3000),
+])
+def test_device_setup_equals_host_setup(ctx, maker):
+    """The device build (affinities, Galerkin products, renumbering on the
+    GPU) gives the host build's hierarchy bit for bit."""
+    import paper_1607_02955_amd as cfc
+    eg = maker()
+    say("device setup", eg.name, eg.n, eg.m)
+    gh = cfc.Graph.from_edgelist(ctx, eg)
+    gh.build_hierarchy(coarsest_max=64, device=0)
+    gd = cfc.Graph.from_edgelist(ctx, eg)
+    gd.build_hierarchy(coarsest_max=64, device=1)
+    ih, idv = gh.info(), gd.info()
+    assert ih["level_n"] == idv["level_n"] and ih["level_nnz"] == idv["level_nnz"]
+    assert ih["eliminated"] == idv["eliminated"]
+    for l in range(ih["levels"]):
+        a, b = gh.level(l), gd.level(l)
+        for k in ("row_ptr", "col", "agg", "agg_ptr", "perm", "elim_nb"):
+            if a[k] is None:
+                assert b[k] is None, (l, k)
+            else:
+                assert np.array_equal(a[k], b[k]), (l, k)
+        for k in ("w", "deg", "coarse_pinv"):
+            if a[k] is not None:
+                assert np.array_equal(a[k].view(np.uint64), b[k].view(np.uint64)), (l, k)
+    s = np.arange(0, eg.n, max(1, eg.n // 50))
+    t = (s * 7 + 1) % eg.n
+    np.testing.assert_array_equal(gh.resistance(s, t, block=64, levels=2),
+                                  gd.resistance(s, t, block=64, levels=2))
