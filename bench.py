@@ -16,7 +16,8 @@ to 1e-10), rmat20_sampling (Sampling, 1000 pivots x 64 nodes, R-MAT scale 20),
 road2048_jl256 (projection k = 256 on a perturbed 2048^2 road grid),
 ba100k_shared1000 (shared-pivot Sampling), ba100k_cfb4096 (sampled
 current-flow betweenness), ba100k_spanning_jl512 (projection spanning-edge
-centrality of every edge) and serve_mix (the serving loop).
+centrality of every edge), serve_mix (the serving loop) and setup_times
+(hierarchy setup, host build vs device build).
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (algorithmic bytes per launch over its HIP-event-timed duration on the launch
@@ -255,6 +256,43 @@ def cpu_baseline(eg, spec, budget_s=20.0):
             ctxm.__exit__(None, None, None)
 
 
+def setup_times(args):
+    """Hierarchy setup (host C++ build vs the device build) on the BA-100k,
+    R-MAT-20 and road-2048^2 graphs; each build is timed after a warm-up
+    build of the same graph."""
+    import torch
+
+    import paper_1607_02955_amd as cfc
+    import synth
+
+    ctx = cfc.Context(0)
+    rows = []
+    for name, fn, a in [("ba100000", synth.barabasi_albert, (100000, 4)), ("rmat20", synth.rmat, (20, 16)),
+                        ("road2048", synth.road_grid, (2048,))]:
+        eg = synth.cached(name, fn, *a, seed=1)
+        print(f"# {name}: n={eg.n} m={eg.m}", file=sys.stderr, flush=True)
+        t = {}
+        for dev in (1, 0, 1):
+            g = cfc.Graph.from_edgelist(ctx, eg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.build_hierarchy(device=dev)
+            torch.cuda.synchronize()
+            t["device" if dev else "host"] = time.perf_counter() - t0
+            info = g.info()
+            print(f"#   {'device' if dev else 'host'} build {t['device' if dev else 'host']:.2f} s",
+                  file=sys.stderr, flush=True)
+            del g
+        rows.append({"graph": name, "n": eg.n, "m": eg.m, "levels": info["levels"],
+                     "eliminated": info["eliminated"], "host_s": round(t["host"], 3),
+                     "device_s": round(t["device"], 3), "speedup": round(t["host"] / t["device"], 2)})
+    out = {"metric": "hierarchy setup seconds (device build)", "value": rows[1]["device_s"], "unit": "s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * rows[1]["device_s"], 1),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "setup_times", "graphs": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +335,9 @@ def main():
 
     if args.workload == "serve_mix":
         serve_mix(args)
+        return
+    if args.workload == "setup_times":
+        setup_times(args)
         return
 
     import paper_1607_02955_amd as cfc
