@@ -126,6 +126,14 @@ typedef struct {
                             is bit-identical to the host build), 0 = host
                             only.  Host-only contexts always build on the
                             host. */
+  int32_t order;         /* locality keys of the nested renumbering:
+                            1 = Cuthill-McKee sweep, 2 = input node order,
+                            3 = descending degree (hubs first, which keeps
+                            the most gathered rows together); 0 = auto
+                            (default): descending degree when the largest
+                            degree exceeds 32 times the mean, else the
+                            Cuthill-McKee sweep */
+  int32_t pad;
 } cfc_setup_params;
 
 typedef struct {

@@ -52,6 +52,8 @@ cfc_setup_params default_setup() {
   p.seed = 1;
   p.eliminate = 1;
   p.device = 1;
+  p.order = 0;
+  p.pad = 0;
   return p;
 }
 
@@ -419,6 +421,7 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
     if (B[0].n > p.coarsest_max && eliminate(B[0], p.eliminate, R)) B.push_back(std::move(R));
   }
   if (p.device != 0 && p.device != 1) fail(CFC_E_INVALID, "device must be 0 or 1");
+  if (p.order < 0 || p.order > 3) fail(CFC_E_INVALID, "order must be 0, 1, 2 or 3");
   std::unique_ptr<DeviceSetup> dev;
   std::vector<int> dh;  // device handle of each build level
   if (p.device && !g.ctx->host_only()) {
@@ -458,7 +461,20 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   // coarse node gets the smallest key of its aggregate.
   auto tk = std::chrono::steady_clock::now();
   std::vector<std::vector<int64_t>> key(L);
-  key[0] = bfs_keys(B[0]);
+  int key_order = p.order;
+  if (key_order == 0) {
+    int64_t maxd = 0;
+    for (int64_t u = 0; u < B[0].n; ++u) maxd = std::max<int64_t>(maxd, B[0].rowptr[u + 1] - B[0].rowptr[u]);
+    const double mean = B[0].n ? (double)B[0].col.size() / (double)B[0].n : 0.0;
+    key_order = (double)maxd > 32.0 * mean ? 3 : 1;
+  }
+  if (key_order == 1) {
+    key[0] = bfs_keys(B[0]);
+  } else {
+    key[0].resize(B[0].n);
+    for (int64_t u = 0; u < B[0].n; ++u)
+      key[0][u] = key_order == 2 ? u : -(int64_t)(B[0].rowptr[u + 1] - B[0].rowptr[u]) * B[0].n + u;
+  }
   for (int l = 0; l + 1 < L; ++l) {
     key[l + 1].assign(B[l + 1].n, INT64_MAX);
     for (int64_t u = 0; u < B[l].n; ++u) {
