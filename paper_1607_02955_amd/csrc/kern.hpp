@@ -66,7 +66,7 @@ struct KernTable {
   int (*rows_grid)(const LevelArgs&, int units);
   // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q
   void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, const double* scal,
-                  int first, double* part, hipStream_t);
+                  int first, double* part, int jac, hipStream_t);
   // Level-0 update and pre-smooth/residual/restrict:
   //   update: r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, partials |r_out|^2, sum x
   //   restrict (if nagg > 0): bc[I] = sum_{u in I} (b - L S b)_u with b = r_out, S = omega D^-1

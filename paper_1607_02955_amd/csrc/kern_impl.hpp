@@ -260,8 +260,10 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
 }
 
 // ---------------------------------------------------------------------------
-// PCG step on level 0: q = L z + beta q, p = z + beta p; partial p.q
-template <typename T, int W, int SPLIT>
+// PCG step on level 0: q = L z + beta q, p = z + beta p; partial p.q.
+// JAC: the preconditioner is one Jacobi step, and z = S r is formed on the
+// fly from the residual passed in place of z (saves storing z).
+template <typename T, int W, bool JAC, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __restrict__ z,
                                                     T* __restrict__ p, T* __restrict__ q,
                                                     const double* __restrict__ scal, int first,
@@ -275,6 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* w = static_cast<const T*>(L.w);
   const T* deg = static_cast<const T*>(L.deg);
+  const T* sd = static_cast<const T*>(L.sd);
   T beta[V];
   double acc[V];
 #pragma unroll
@@ -290,13 +293,25 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
 #pragma unroll
     for (int i = 0; i < V; ++i) nb[i] = 0;
     if (u < L.n)
-      gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT,
-                       [&](int v) { return ld<T, V>(z + (size_t)v * W + c0); });
+      gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT, [&](int v) {
+        Vec<T, V> zv = ld<T, V>(z + (size_t)v * W + c0);
+        if constexpr (JAC) {
+          const T f = sd[v];
+#pragma unroll
+          for (int i = 0; i < V; ++i) zv.v[i] *= f;
+        }
+        return zv;
+      });
     if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(nb, ldc);
     if (u < L.n && D::leader(rg)) {
       add_heavy<T, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
-      const Vec<T, V> zu = ld<T, V>(z + o);
+      Vec<T, V> zu = ld<T, V>(z + o);
+      if constexpr (JAC) {
+        const T f = sd[u];
+#pragma unroll
+        for (int i = 0; i < V; ++i) zu.v[i] *= f;
+      }
       const T du = deg[u];
       Vec<T, V> pn, qn;
       if (first) {
@@ -500,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
       xo.v[i] = su * bu.v[i];
       if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
     }
-    st<T, V>(x + o, xo);
+    if (x) st<T, V>(x + o, xo);
   }
   if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
@@ -551,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     }
     st_nt<T, V>(x + o, xu);
     st_nt<T, V>(r_out + o, rn);
-    st<T, V>(z + o, zu);
+    if (z) st<T, V>(z + o, zu);
   }
   block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
   block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
@@ -1122,10 +1137,15 @@ struct Launch {
   }
 
   static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, const double* scal,
-                      int first, double* part, hipStream_t s) {
-    heavy<HK_SPMM>(L, z, nullptr, nullptr, scal, s);
+                      int first, double* part, int jac, hipStream_t s) {
 #define ARGS L, (const T*)z, (T*)p, (T*)q, scal, first, part
-    CFC_LAUNCH(k_spmm_pq, L.n, T, W);
+    if (jac) {
+      heavy<HK_RESTRICT>(L, z, nullptr, nullptr, scal, s);  // sum of w_e sd_v r_v
+      CFC_LAUNCH(k_spmm_pq, L.n, T, W, true);
+    } else {
+      heavy<HK_SPMM>(L, z, nullptr, nullptr, scal, s);
+      CFC_LAUNCH(k_spmm_pq, L.n, T, W, false);
+    }
 #undef ARGS
   }
   static void update_restrict(const LevelArgs& L, const void* r_in, const void* q, const void* p,

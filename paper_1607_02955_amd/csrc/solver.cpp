@@ -337,15 +337,15 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     // depth one: Jacobi-preconditioned CG, z = S r
     if (update) {
       prof_begin(K_RESTRICT0);
-      k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.z.p, w.scal.as<double>(), first_x,
+      k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
                       w.part_ptr(P_RR), w.part_ptr(P_CS), w.part_ptr(P_RZ), s);
-      const double ub = d0.n * nw * (first_x ? 6 : 7) + 2.0 * es * d0.n;
+      const double ub = d0.n * nw * (first_x ? 5 : 6) + 2.0 * es * d0.n;
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
       g_rr = g_cs = grid_for(d0.n, k.rg);
     } else {
-      k.jacobi(w.la[0], r_in, w.z.p, w.part_ptr(P_RZ), s);
-      bytes += d0.n * nw * 2 + es * d0.n;
+      k.jacobi(w.la[0], r_in, nullptr, w.part_ptr(P_RZ), s);  // r . S r only
+      bytes += d0.n * nw + es * d0.n;
     }
     g_rz = grid_for(d0.n, k.rg);
     return;
@@ -519,8 +519,11 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
   const double nw = (double)w.W * es;
   const int W = w.W;
   prof_begin(K_SPMM);
-  k.spmm_pq(w.la[0], w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first, w.part_ptr(P_PQ), stream);
-  const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es);
+  // depth one: z = S r_in is formed inside the product kernel
+  const bool jac = nuse == 1 && w.nlev > 1;
+  k.spmm_pq(w.la[0], jac ? r_in : w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first, w.part_ptr(P_PQ),
+            jac ? 1 : 0, stream);
+  const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) + (jac ? es * d0.n : 0.0);
   prof_end(K_SPMM, sb);
   bytes += sb;
   finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
