@@ -757,16 +757,32 @@ __global__ __launch_bounds__(kBlock) void k_jl_rhs(LevelArgs L, const int* __res
     const int e1 = hh >= 0 ? L.hptr[hh + 1] : L.rowptr[u + 1];
     const int* cl = hh >= 0 ? L.hcol : L.col;
     const double* wl = hh >= 0 ? static_cast<const double*>(L.hw) : w;
-    for (int e = e0; e < e1; ++e) {
-      const uint64_t gv = uint64_t(iperm[cl[e]]);
-      const uint64_t lo = gu < gv ? gu : gv, hi = gu < gv ? gv : gu;
-      const double sw = wl ? sqrt(wl[e]) : 1.0;
-      const double sg = gu < gv ? sw : -sw;
-      const uint64_t h = jl_word(seed, word, lo, hi);
+    // The row group's columns lie in one 64-column sign word (WS divides 64
+    // and every slice starts on a multiple of WS), so lane j hashes edge
+    // eb + j once and the group shares the words through shuffles.
+    const int lane = threadIdx.x % LPR;
+    for (int eb = e0; eb < e1; eb += LPR) {
+      const int e = eb + lane;
+      uint64_t h = 0;
+      double sg = 0;
+      if (e < e1) {
+        const uint64_t gv = uint64_t(iperm[cl[e]]);
+        const uint64_t lo = gu < gv ? gu : gv, hi = gu < gv ? gv : gu;
+        const double sw = wl ? sqrt(wl[e]) : 1.0;
+        sg = gu < gv ? sw : -sw;
+        h = jl_word(seed, word, lo, hi);
+      }
+      const unsigned hl = (unsigned)h, hu = (unsigned)(h >> 32);
+      const int cnt = min(LPR, e1 - eb);
+      for (int j = 0; j < cnt; ++j) {
+        const uint64_t hj = ((uint64_t)(unsigned)__shfl((int)hu, j, LPR) << 32) |
+                            (uint64_t)(unsigned)__shfl((int)hl, j, LPR);
+        const double sgj = __shfl(sg, j, LPR);
 #pragma unroll
-      for (int i = 0; i < V; ++i) {
-        const int bit = int((h >> ((sys0 + i) & 63)) & 1u);
-        a[i] += bit ? -sg : sg;
+        for (int i = 0; i < V; ++i) {
+          const int bit = int((hj >> ((sys0 + i) & 63)) & 1u);
+          a[i] += bit ? -sgj : sgj;
+        }
       }
     }
     Vec<double, V> yo;
