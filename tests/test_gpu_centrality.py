@@ -184,3 +184,36 @@ def test_current_throughput_raw_pairs(ctx):
     a, b = cfc.random_pairs(4, eg.n, 50)
     ao, bo = ORNG.random_pairs(4, eg.n, 50)
     assert a.tolist() == ao.tolist() and b.tolist() == bo.tolist()
+
+
+def test_centrality_edge_cases(ctx):
+    import paper_1607_02955_amd as cfc
+    g = load(ctx, synth.path_graph(3))
+    np.testing.assert_allclose(g.cfb_exact(tol=1e-10), [0.0, 1.0, 0.0], atol=1e-9)
+    np.testing.assert_allclose(g.current_throughput([], [], tol=1e-10), 0.0)
+    assert g.spanning_edge([], []).shape == (0,)
+    np.testing.assert_allclose(g.spanning_edge([0, 1], [1, 2], tol=1e-10), [1.0, 1.0], rtol=1e-9)
+    far, clo = g.farness_sampling_shared([], 2, 1)
+    assert far.shape == (0,)
+    far, clo = g.farness_sampling_shared([0, 1, 2], 10, 1, tol=1e-10)  # k clamped to n: exact
+    np.testing.assert_allclose(far, [3.0, 2.0, 3.0], rtol=1e-9)
+    with pytest.raises(cfc.CfcError):
+        g.cfb_sampled(0)
+    with pytest.raises(cfc.CfcError):
+        g.farness_sampling_shared([3], 2, 1)
+    with pytest.raises(cfc.CfcError):
+        g.current_throughput([0], [3])
+    g2 = load(ctx, synth.path_graph(2))
+    with pytest.raises(cfc.CfcError):
+        g2.cfb_exact()
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_locality_orders_same_resistances(ctx, order):
+    eg = synth.rmat(12, seed=2)
+    g = load(ctx, eg, coarsest_max=64, order=order)
+    rng = np.random.default_rng(order)
+    s = rng.integers(0, eg.n, 100)
+    t = rng.integers(0, eg.n, 100)
+    Rm = R.resistance_matrix(R.pinv(LAP.of(eg, dense=True)))
+    np.testing.assert_allclose(g.resistance(s, t, tol=1e-10, precision=1), Rm[s, t], rtol=1e-8, atol=1e-12)

@@ -22,19 +22,20 @@ def setup():
     import paper_1607_02955_amd as cfc
     ctx = cfc.Context(0)
     egs = [synth.barabasi_albert(3000, 4, seed=5), synth.road_grid(50, seed=6),
-           synth.random_connected(2000, 7000, seed=7)]
+           synth.random_connected(2000, 7000, seed=7), synth.rmat(12, seed=8)]
     gs = [cfc.Graph.from_edgelist(ctx, eg).build_hierarchy(coarsest_max=64) for eg in egs]
+    assert gs[3].info()["eliminated"] > 0  # one graph with an elimination level
     return cfc, ctx, egs, gs
 
 
 def queries(egs):
     rng = np.random.default_rng(3)
     out = []
-    for i in range(12):
+    for i in range(16):
         gi = i % len(egs)
         nn = int(rng.integers(1, 6))
         nodes = rng.choice(egs[gi].n, nn, replace=False)
-        kind = i % 2
+        kind = (i + i // len(egs)) % 2
         out.append((gi, kind, nodes, 30 + 5 * (i % 3)))
     return out
 

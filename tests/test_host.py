@@ -224,3 +224,33 @@ def test_random_pairs_match_oracle():
         s, t = cfc.random_pairs(seed, n, 300)
         so, to = ORNG.random_pairs(seed, n, 300)
         assert s.tolist() == so.tolist() and t.tolist() == to.tolist()
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_locality_orders_give_valid_nested_hierarchies(hctx, order):
+    """Every locality order yields a permutation of the nodes with contiguous
+    aggregates, and the same level sizes (the order only renumbers)."""
+    eg = synth.barabasi_albert(2500, 4, seed=4)
+    ref = cfc.Graph.from_edgelist(hctx, eg).build_hierarchy(coarsest_max=64, order=1)
+    g = cfc.Graph.from_edgelist(hctx, eg).build_hierarchy(coarsest_max=64, order=order)
+    assert g.info()["level_n"] == ref.info()["level_n"]
+    assert g.info()["level_nnz"] == ref.info()["level_nnz"]
+    lv0 = g.level(0)
+    assert sorted(lv0["perm"].tolist()) == list(range(eg.n))
+    Lin = LAP.of(eg).toarray()
+    p = lv0["perm"]
+    np.testing.assert_allclose(_level_laplacian(lv0)[np.ix_(p, p)], Lin, atol=1e-12)
+    for l in range(g.info()["levels"] - 1):
+        agg = g.level(l)["agg"]
+        assert np.all(np.diff(agg) >= 0)
+    if order == 3:  # hubs first: row 0 holds a node of maximum degree
+        deg = np.diff(LAP.of(eg).indptr)
+        assert deg[np.argsort(p)[0]] == deg.max()
+
+
+def test_setup_param_errors(hctx):
+    eg = synth.path_graph(10)
+    g = cfc.Graph.from_edgelist(hctx, eg)
+    for kw in ({"order": 4}, {"eliminate": 3}, {"device": 2}):
+        with pytest.raises(cfc.CfcError):
+            g.build_hierarchy(**kw)
