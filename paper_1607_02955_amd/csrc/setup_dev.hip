@@ -45,38 +45,41 @@ __global__ void k_testvec(int64_t n, int K, uint64_t seed, int level, double* __
   X[i] = double(h >> 11) * 0x1.0p-53 * 2.0 - 1.0;
 }
 
-// one damped Jacobi sweep on L x = 0 for every test vector (row per thread,
-// edges in CSR order, eight vectors per pass)
+// one damped Jacobi sweep on L x = 0 for every test vector: thread (u, k),
+// edges in CSR order (the host's order for every (u, k))
 __global__ void k_relax(int64_t n, int K, const int32_t* __restrict__ rowptr,
                         const int32_t* __restrict__ col, const double* __restrict__ w,
                         const double* __restrict__ deg, const double* __restrict__ X,
                         double* __restrict__ Y, double om) {
 #pragma clang fp contract(off)
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * K) return;
+  const int64_t u = i / K;
+  const int k = (int)(i % K);
   const double du = deg[u];
   const double sc = du > 0 ? om / du : 0.0;
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    const int kn = min(8, K - k0);
-    double acc[8];
-    for (int k = 0; k < kn; ++k) acc[k] = du * X[u * K + k0 + k];
-    for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
-      const double we = w[e];
-      const double* xv = X + (int64_t)col[e] * K + k0;
-      for (int k = 0; k < kn; ++k) acc[k] -= we * xv[k];
-    }
-    for (int k = 0; k < kn; ++k) Y[u * K + k0 + k] = X[u * K + k0 + k] - sc * acc[k];
-  }
+  double acc = du * X[i];
+  for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) acc -= w[e] * X[(int64_t)col[e] * K + k];
+  Y[i] = X[i] - sc * acc;
 }
 
-// mean of column k, summed in node order by one thread (as the host does)
-__global__ void k_colmean(int64_t n, int K, const double* __restrict__ X, double* __restrict__ mean) {
+// mean of column k, summed in node order by one thread (as the host does);
+// the workgroup stages chunks of the column in LDS for that thread
+__global__ __launch_bounds__(256) void k_colmean(int64_t n, int K, const double* __restrict__ X,
+                                                 double* __restrict__ mean) {
 #pragma clang fp contract(off)
-  const int k = threadIdx.x;
-  if (k >= K) return;
+  __shared__ double buf[1024];
+  const int k = blockIdx.x;
   double s = 0;
-  for (int64_t u = 0; u < n; ++u) s += X[u * K + k];
-  mean[k] = s / double(n);
+  for (int64_t base = 0; base < n; base += 1024) {
+    const int64_t cnt = n - base < 1024 ? n - base : 1024;
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) buf[j] = X[(base + j) * K + k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int j = 0; j < cnt; ++j) s += buf[j];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[k] = s / double(n);
 }
 
 __global__ void k_center(int64_t n, int K, double* __restrict__ X, const double* __restrict__ mean,
@@ -259,12 +262,12 @@ std::vector<double> DeviceSetup::affinities(int lv, int level, const cfc_setup_p
                      X.as<double>());
   const double om = 0.6;  // the host build's relaxation weight
   for (int sw = 0; sw < p.relax_sweeps; ++sw) {
-    hipLaunchKernelGGL(k_relax, dim3(blocks_for(n)), dim3(kT), 0, s, n, K, c.rowptr.as<int32_t>(),
+    hipLaunchKernelGGL(k_relax, dim3(blocks_for(n * K)), dim3(kT), 0, s, n, K, c.rowptr.as<int32_t>(),
                        c.col.as<int32_t>(), c.w.as<double>(), c.deg.as<double>(), X.as<double>(),
                        Y.as<double>(), om);
     std::swap(X.p, Y.p);
   }
-  hipLaunchKernelGGL(k_colmean, dim3(1), dim3(64), 0, s, n, K, X.as<double>(), mean.as<double>());
+  hipLaunchKernelGGL(k_colmean, dim3(K), dim3(256), 0, s, n, K, X.as<double>(), mean.as<double>());
   hipLaunchKernelGGL(k_center, dim3(blocks_for(n)), dim3(kT), 0, s, n, K, X.as<double>(),
                      mean.as<double>(), nx.as<double>());
   if (c.nnz)
