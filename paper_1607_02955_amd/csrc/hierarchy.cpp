@@ -401,7 +401,24 @@ std::vector<int64_t> bfs_keys(const BLevel& L) {
 
 }  // namespace
 
+namespace {
+void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device);
+}
+
 void build_hierarchy(Graph& g, const cfc_setup_params& p) {
+  const bool on_device = p.device == 1 && !g.ctx->host_only();
+  try {
+    build_hierarchy_impl(g, p, on_device);
+  } catch (const Error& e) {
+    // a device build that runs out of device memory falls back to the host
+    // build (same hierarchy); anything else is reported
+    if (!on_device || e.code != CFC_E_NOMEM) throw;
+    build_hierarchy_impl(g, p, false);
+  }
+}
+
+namespace {
+void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
   auto t0 = std::chrono::steady_clock::now();
   if (p.coarsest_max < 1 || p.coarsest_max > 4096) fail(CFC_E_INVALID, "coarsest_max must be in [1, 4096]");
   if (p.agg_cap < 2 || p.agg_cap > 64) fail(CFC_E_INVALID, "agg_cap must be in [2, 64]");
@@ -424,7 +441,7 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   if (p.order < 0 || p.order > 3) fail(CFC_E_INVALID, "order must be 0, 1, 2 or 3");
   std::unique_ptr<DeviceSetup> dev;
   std::vector<int> dh;  // device handle of each build level
-  if (p.device && !g.ctx->host_only()) {
+  if (on_device) {
     dev = std::make_unique<DeviceSetup>(g.ctx);
     for (const BLevel& b : B) dh.push_back(dev->add(b));
   }
@@ -617,5 +634,6 @@ void build_hierarchy(Graph& g, const cfc_setup_params& p) {
   g.H = std::move(H);
   g.have_h = true;
 }
+}  // namespace
 
 }  // namespace cfc
