@@ -133,23 +133,33 @@ __device__ __forceinline__ T wt(const T* w, int e) {
 }
 
 // nb += sum over edges e = e0 + s, e0 + s + S, ... < e1 of w_e * f(col_e),
-// four neighbour rows in flight.  f returns the neighbour's WS-slice values.
+// kGatherDepth neighbour rows in flight, added in edge order (so the depth
+// does not change the result).  f returns the neighbour's WS-slice values.
+#ifndef CFC_GATHER_DEPTH
+#define CFC_GATHER_DEPTH 4
+#endif
+constexpr int kGatherDepth = CFC_GATHER_DEPTH;
+
 template <typename T, int W, class F>
 __device__ __forceinline__ void gather_acc(T* nb, const int* __restrict__ col, const T* __restrict__ w,
                                            int e0, int e1, int s, int S, F&& f) {
-  constexpr int V = Shape<W>::V;
+  constexpr int V = Shape<W>::V, D = kGatherDepth;
   int e = e0 + s;
-  for (; e + 3 * S < e1; e += 4 * S) {
-    const int v0 = col[e], v1 = col[e + S], v2 = col[e + 2 * S], v3 = col[e + 3 * S];
-    const T w0 = wt(w, e), w1 = wt(w, e + S), w2 = wt(w, e + 2 * S), w3 = wt(w, e + 3 * S);
-    const Vec<T, V> x0 = f(v0), x1 = f(v1), x2 = f(v2), x3 = f(v3);
+  for (; e + (D - 1) * S < e1; e += D * S) {
+    int v[D];
+    T wv[D];
+    Vec<T, V> x[D];
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      nb[i] += w0 * x0.v[i];
-      nb[i] += w1 * x1.v[i];
-      nb[i] += w2 * x2.v[i];
-      nb[i] += w3 * x3.v[i];
+    for (int j = 0; j < D; ++j) {
+      v[j] = col[e + j * S];
+      wv[j] = wt(w, e + j * S);
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = f(v[j]);
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) nb[i] += wv[j] * x[j].v[i];
   }
   for (; e < e1; e += S) {
     const int v0 = col[e];
