@@ -131,8 +131,10 @@ int grid_for(int units, int rows_per_block);
 // Sum partials[g][W] over g (fixed order) into scal rows; op selects the
 // scalar update (see Finalize in kern_impl.hpp).
 enum FinOp { F_ALPHA = 0, F_RZINIT = 1, F_BETA = 2, F_R64 = 3, F_CS = 4 };
+// host (nullable): device address of host-mapped memory [S_N][W] that also
+// receives the S_RR and S_R64 rows, so the host reads them without a copy.
 void finalize(int W, int op, int g0, const double* p0, int g1, const double* p1, int g2,
-              const double* p2, double* scal, hipStream_t s);
+              const double* p2, double* scal, hipStream_t s, double* host = nullptr);
 // out[j] = x64[s_j, j] - x64[t_j, j] for j < ncols
 void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt, double* out,
                hipStream_t s);

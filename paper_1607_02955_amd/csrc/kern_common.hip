@@ -74,7 +74,7 @@ __device__ __forceinline__ double sum_rows(const double* __restrict__ p, int G, 
 __global__ __launch_bounds__(256) void k_finalize(int W, int op, int g0, const double* __restrict__ p0,
                                                   int g1, const double* __restrict__ p1, int g2,
                                                   const double* __restrict__ p2,
-                                                  double* __restrict__ scal) {
+                                                  double* __restrict__ scal, double* __restrict__ host) {
   const int CH = W < FCH ? W : FCH;
   const int S = 256 / CH;
   const int tid = threadIdx.x;
@@ -116,10 +116,12 @@ __global__ __launch_bounds__(256) void k_finalize(int W, int op, int g0, const d
       scal[S_RZ * W + c] = t0;
       scal[S_RR * W + c] = t1;
       scal[S_CS * W + c] = t2;
+      if (host) host[S_RR * W + c] = t1;  // read by the host's convergence test
       break;
     }
     case F_R64:
       scal[S_R64 * W + c] = t0;
+      if (host) host[S_R64 * W + c] = t0;
       break;
     case F_CS:
       scal[S_CS * W + c] = t0;
@@ -201,10 +203,10 @@ void zero_fill(void* p, size_t bytes, hipStream_t s) {
 }
 
 void finalize(int W, int op, int g0, const double* p0, int g1, const double* p1, int g2,
-              const double* p2, double* scal, hipStream_t s) {
+              const double* p2, double* scal, hipStream_t s, double* host) {
   const int CH = W < FCH ? W : FCH;
   hipLaunchKernelGGL(k_finalize, dim3((W + CH - 1) / CH), dim3(256), 0, s, W, op, g0, p0, g1, p1,
-                     g2, p2, scal);
+                     g2, p2, scal, host);
 }
 
 void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt, double* out,

@@ -254,6 +254,7 @@ static LevelArgs fwd_args(const Graph& g, bool fp64) {
 
 Workspace::~Workspace() {
   if (pinned) (void)hipHostFree(pinned);
+  if (mirror) (void)hipHostFree(mirror);
 }
 
 Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem) {
@@ -304,6 +305,9 @@ Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem) {
   w.scal.alloc(c, (size_t)S_N * W * sizeof(double));
   w.dvec.alloc(c, (size_t)(W + 1024) * sizeof(double));
   CFC_HIP(hipHostMalloc(&w.pinned, (size_t)(4 * W + 64) * sizeof(double), hipHostMallocDefault));
+  CFC_HIP(hipHostMalloc(&w.mirror, (size_t)S_N * W * sizeof(double),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  CFC_HIP(hipHostGetDevicePointer((void**)&w.mirror_dev, w.mirror, 0));
   w.kt->zero(w.scal.p, w.scal.bytes, s);
   w.kt->zero(w.part.p, w.part.bytes, s);
   g.ws.push_back(std::move(ws));
@@ -506,6 +510,12 @@ void Solver::prof_collect() {
 // Read the per-column squared residuals S_RR to the host (synchronises).
 void Solver::read_scal(int which, double* out) {
   Workspace& w = *ws;
+  if (which == S_RR || which == S_R64) {
+    // written to host-mapped memory by the finalize step
+    CFC_HIP(hipStreamSynchronize(stream));
+    std::memcpy(out, w.mirror + (size_t)which * w.W, w.W * sizeof(double));
+    return;
+  }
   CFC_HIP(hipMemcpyAsync(w.pinned, w.scal.as<double>() + (size_t)which * w.W, w.W * sizeof(double),
                          hipMemcpyDeviceToHost, stream));
   CFC_HIP(hipStreamSynchronize(stream));
@@ -533,7 +543,7 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
            w.scal.as<double>(), stream);
   vcycle(true, first, r_in, r_out);
   finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
-           w.scal.as<double>(), stream);
+           w.scal.as<double>(), stream, w.mirror_dev);
 }
 
 void Solver::capture_pair() {
@@ -615,7 +625,8 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     k.residual64(w.la64, have_x ? w.x64.as<double>() : nullptr, rhs, w.ra.p, w.part_ptr(P_PQ), s);
     bytes += d0.n * (double)W * ((have_x ? 8.0 : 0.0) + (rhs.kind == 0 ? 8.0 : 0.0) + es) +
              (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
-    finalize(W, F_R64, gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s);
+    finalize(W, F_R64, gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s,
+             w.mirror_dev);
     read_scal(S_R64, r64.data());
     if (step == 0) b2 = r64;
     bool all = true;

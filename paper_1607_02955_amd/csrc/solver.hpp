@@ -30,6 +30,8 @@ struct Workspace {
   DBuf scal;                  // FP64 per-column scalars [S_N][W]
   DBuf dvec;                  // FP64 scratch for per-column outputs
   double* pinned = nullptr;   // pinned host staging
+  double* mirror = nullptr;   // host-mapped [S_N][W]: S_RR, S_R64 as finalized
+  double* mirror_dev = nullptr;  // its device address
   ~Workspace();
   double* part_ptr(int which) const;
 };
