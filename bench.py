@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--block", type=int, default=-1, help="block width W (default: the workload's)")
     ap.add_argument("--use-graph", type=int, default=-1,
                     help="replay PCG iterations from a HIP graph (1/0; default: on for n < 100000)")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="PCG relative reduction per refinement step (0 = autotuned)")
     ap.add_argument("--check-every", type=int, default=1,
                     help="PCG iterations between host convergence checks")
     ap.add_argument("--duration", type=float, default=30.0, help="serve_mix: seconds of arrivals")
@@ -363,7 +365,7 @@ def main():
     if args.block >= 0:
         spec["block"] = args.block
     kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels,
-              use_graph=use_graph, check_every=args.check_every)
+              use_graph=use_graph, check_every=args.check_every, inner_tol=args.inner_tol)
 
     def step(seed, **over):
         kw2 = dict(kw, **over)

@@ -143,8 +143,11 @@ typedef struct {
                             0 = autotuned for the graph */
   int32_t max_refine;    /* FP64 refinement steps (20) */
   int32_t max_inner;     /* PCG iterations per refinement step (300) */
-  double inner_tol;      /* PCG relative reduction per refinement step (1e-3;
-                            FP64 mode uses tol) */
+  double inner_tol;      /* PCG relative reduction per refinement step (at
+                            least the one that reaches tol); 0 = autotuned
+                            (default): 1e-4 (FP32 inner solves, two
+                            refinement steps to 1e-6) or 1e-7 (straight to
+                            the target) by timing both on sample columns */
   int32_t use_graph;     /* 1 = replay a captured HIP graph per PCG iteration */
   int32_t check_every;   /* PCG iterations between host convergence checks (1) */
   int32_t levels;        /* V-cycle depth: hierarchy levels used by the

@@ -86,7 +86,7 @@ def random_pairs(seed: int, n: int, count: int):
 
 
 def solve_params(tol=1e-6, precision=PREC_MIXED, block=0, max_refine=20, max_inner=300,
-                 inner_tol=1e-4, use_graph=0, check_every=1, levels=0) -> _lib.SolveParams:
+                 inner_tol=0.0, use_graph=0, check_every=1, levels=0) -> _lib.SolveParams:
     return _lib.SolveParams(tol, precision, block, max_refine, max_inner, inner_tol, use_graph,
                             check_every, levels, 0)
 

@@ -23,7 +23,7 @@ cfc_solve_params default_solve() {
   p.block = 0;
   p.max_refine = 20;
   p.max_inner = 300;
-  p.inner_tol = 1e-4;
+  p.inner_tol = 0;  // autotuned
   p.use_graph = 0;
   p.check_every = 1;
   p.levels = 0;
@@ -46,7 +46,7 @@ void check_params(const cfc_solve_params& p) {
   if (!(p.tol > 0 && p.tol < 1)) fail(CFC_E_INVALID, "tol must be in (0, 1)");
   if (p.precision != CFC_PREC_MIXED && p.precision != CFC_PREC_FP64) fail(CFC_E_INVALID, "bad precision");
   if (p.max_refine < 0 || p.max_inner < 1) fail(CFC_E_INVALID, "bad iteration limits");
-  if (!(p.inner_tol > 0 && p.inner_tol < 1)) fail(CFC_E_INVALID, "inner_tol must be in (0, 1)");
+  if (!(p.inner_tol >= 0 && p.inner_tol < 1)) fail(CFC_E_INVALID, "inner_tol must be in [0, 1)");
   if (p.block != 0 && !kern_table(p.block, false)) fail(CFC_E_INVALID, "block must be 0, 1, 32, 64, 128, 256 or 512");
   if (p.levels < 0 || p.levels > CFC_MAX_LEVELS) fail(CFC_E_INVALID, "levels must be in [0, 32]");
 }
@@ -94,6 +94,38 @@ static double tune_score(Graph& g, const cfc_solve_params& p0, int W, int depth)
   return score;
 }
 
+// Refinement split: aim each FP32 inner solve at 1e-4 (two refinement steps
+// to 1e-6), or straight at the target (one step, inner floor 1e-7, about
+// FP32 rounding) when the FP32 iteration can get there without stalling.
+// Both are timed on W sample pair right-hand sides to the requested
+// tolerance; one step wins only if every column converges and it is faster.
+constexpr double kTwoStep = 1e-4, kOneStep = 1e-7;
+
+static int tune_split(Graph& g, const cfc_solve_params& p0, int W, int depth) {
+  if (p0.precision == CFC_PREC_FP64) return 0;  // FP64 inner solves aim at the target anyway
+  cfc_solve_params q = p0;
+  q.block = W;
+  q.levels = depth;
+  std::vector<int64_t> s(W), t(W);
+  for (int j = 0; j < W; ++j) {
+    s[j] = (int64_t)((uint64_t(j) * 2654435761ull + 777) % uint64_t(g.n));
+    t[j] = (int64_t)((uint64_t(j) * 40503ull + 91 + uint64_t(g.n) / 3) % uint64_t(g.n));
+    if (s[j] == t[j]) t[j] = (t[j] + 1) % g.n;
+  }
+  std::vector<double> out(W);
+  cfc_solve_stats two{}, one{};
+  q.inner_tol = kTwoStep;
+  for (int rep = 0; rep < 2; ++rep) {
+    two = cfc_solve_stats{};
+    pair_solves(g, W, s.data(), t.data(), out.data(), q, &two, nullptr);
+  }
+  if (two.converged < W) return 0;
+  q.inner_tol = kOneStep;
+  q.max_inner = (int)std::min<int64_t>(q.max_inner, std::max<int64_t>(10, 2 * two.inner_iters));
+  pair_solves(g, W, s.data(), t.data(), out.data(), q, &one, nullptr);
+  return (one.converged == W && one.solve_ms < 0.97 * two.solve_ms) ? 1 : 0;
+}
+
 static bool width_fits(const Graph& g, int W, int prec) {
   double n = 0;
   for (const auto& l : g.D->lv) n += (double)l.n;
@@ -109,13 +141,20 @@ static bool width_fits(const Graph& g, int W, int prec) {
 
 cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p0, int64_t ncols) {
   cfc_solve_params p = p0;
-  if (p.block && p.levels) return p;
+  auto split = [&](int one_step) {
+    if (p0.inner_tol == 0) p.inner_tol = one_step ? kOneStep : kTwoStep;
+  };
+  if (p.block && p.levels) {
+    split(0);
+    return p;
+  }
   const int prec = p.precision;
   const int nlev = (int)g.D->lv.size();
   for (const auto& t : g.tuned)
     if (t[0] == prec && t[1] == p0.block) {
       if (!p.block) p.block = t[2];
       if (!p.levels) p.levels = t[3];
+      split(t[4]);
       return p;
     }
   const char* cache = std::getenv("CFC_TUNE_CACHE");
@@ -126,12 +165,13 @@ cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p0, int64_t ncols
     while (std::getline(f, line)) {
       if (line.rfind(key + " ", 0) != 0) continue;
       std::istringstream is(line.substr(key.size() + 1));
-      int W = 0, d = 0;
-      is >> W >> d;
+      int W = 0, d = 0, one = 0;
+      is >> W >> d >> one;
       if (kern_table(W, false) && d >= 1 && d <= nlev) {
-        g.tuned.push_back({prec, p0.block, W, d});
+        g.tuned.push_back({prec, p0.block, W, d, one ? 1 : 0});
         if (!p.block) p.block = W;
         if (!p.levels) p.levels = d;
+        split(one);
         return p;
       }
     }
@@ -174,15 +214,17 @@ cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p0, int64_t ncols
   g.ws.erase(std::remove_if(g.ws.begin(), g.ws.end(),
                             [&](const std::unique_ptr<Workspace>& w) { return w->W != best_W; }),
              g.ws.end());
+  const int one = p0.inner_tol == 0 ? tune_split(g, p, best_W, best_d) : 0;
   if (!p0.levels) {
-    g.tuned.push_back({prec, p0.block, best_W, best_d});
+    g.tuned.push_back({prec, p0.block, best_W, best_d, one});
     if (cache) {
       std::ofstream f(cache, std::ios::app);
-      f << key << ' ' << best_W << ' ' << best_d << '\n';
+      f << key << ' ' << best_W << ' ' << best_d << ' ' << one << '\n';
     }
   }
   p.block = best_W;
   p.levels = best_d;
+  split(one);
   return p;
 }
 

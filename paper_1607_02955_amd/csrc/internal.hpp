@@ -153,8 +153,8 @@ struct Graph {
   std::unique_ptr<DevHierarchy> D;
   std::vector<std::unique_ptr<Workspace>> ws;
   JLSketch jl;
-  // autotuned (precision, requested W or 0, W, depth)
-  std::vector<std::array<int, 4>> tuned;
+  // autotuned (precision, requested W or 0, W, depth, one-step refinement)
+  std::vector<std::array<int, 5>> tuned;
   std::mutex mu;
   Graph();
   ~Graph();

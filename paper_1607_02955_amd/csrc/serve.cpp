@@ -55,6 +55,7 @@ struct GraphWorker {
   Graph* g = nullptr;
   int gid = 0;
   int depth = 0;                    // V-cycle depth (autotuned at registration)
+  double itol = 1e-4;               // inner tolerance floor (autotuned at registration)
   hipStream_t stream = nullptr;
   std::thread th;
   std::deque<ColTask> pending;      // guarded by srv->mu
@@ -114,6 +115,7 @@ void GraphWorker::run() {
   (void)hipSetDevice(S.ctx->device);
   cfc_solve_params p = serve_params(S.opts);
   p.levels = depth;
+  p.inner_tol = itol;
   const int W = p.block;
   std::unique_ptr<Solver> sol;
   std::vector<ColTask> slot(W);
@@ -338,7 +340,11 @@ int cfc_server_add_graph(cfc_server* s, cfc_graph* gh, int32_t* gid) {
     auto w = std::make_unique<GraphWorker>();
     w->srv = s;
     w->g = g;
-    w->depth = tune_params(*g, serve_params(s->opts), s->opts.slots).levels;
+    {
+      const cfc_solve_params tp = tune_params(*g, serve_params(s->opts), s->opts.slots);
+      w->depth = tp.levels;
+      w->itol = tp.inner_tol;
+    }
     // workspaces the graph holds from direct calls (and the tuning runs) were
     // allocated with the caller's allocator: release them on this thread
     CFC_HIP(hipStreamSynchronize(s->ctx->stream));
