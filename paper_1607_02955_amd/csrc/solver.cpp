@@ -643,8 +643,14 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
                    cur_max, rel[0]);
     }
     if (all || step >= p.max_refine) break;
-    double itol = p.precision == CFC_PREC_FP64 ? std::max(0.5 * p.tol / cur_max, 1e-15)
-                                                : std::max(p.inner_tol, 0.5 * p.tol / cur_max);
+    // Inner target as a fraction of what is left to reach tol: 0.9 when the
+    // inner solve can be trusted to land near it (FP64 inner solves, or FP32
+    // ones aimed straight at the target, inner_tol < 1e-6); 0.5 when FP32
+    // rounding may leave the true residual above the recursive one.
+    const bool direct = p.precision == CFC_PREC_FP64 || p.inner_tol < 1e-6;
+    const double aim = direct ? 0.9 : 0.5;
+    double itol = p.precision == CFC_PREC_FP64 ? std::max(aim * p.tol / cur_max, 1e-15)
+                                                : std::max(p.inner_tol, aim * p.tol / cur_max);
     itol = std::min(itol, 0.5);
     const int its = pcg(r64, itol, p.max_inner, std::max(1, p.check_every));
     if (debug) std::fprintf(stderr, "[cfc]   pcg its %d (inner tol %.2e)\n", its, itol);
