@@ -57,9 +57,10 @@ void check_params(const cfc_solve_params& p) {
 // sides for one refinement step (inner tolerance 1e-3, at most 100 PCG
 // iterations) and is scored by solve time / (W * decades of residual
 // reduction), after a warm-up run.  Depth is chosen first at W = 256 (or
-// the fixed W), then W at that depth.  Results are cached in the graph and,
-// when CFC_TUNE_CACHE names a file, on disk as "n nnz levels precision
-// requested-W W depth" lines.
+// the fixed W), then W at that depth, then (inner_tol = 0) the refinement
+// split (tune_split below).  Results are cached in the graph and, when
+// CFC_TUNE_CACHE names a file, on disk as "n nnz levels precision
+// requested-W W depth one-step" lines.
 
 static std::string tune_key(const Graph& g, int prec) {
   std::ostringstream o;
