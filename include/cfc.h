@@ -235,8 +235,10 @@ void cfc_graph_destroy(cfc_graph* g);
 
 /* Build the aggregation multigrid hierarchy used by every solve (the
  * solver's setup phase; the paper's solver coarsens by aggregating nodes by
- * an affinity measure, Sec. 3.1).  Host work; uploads to the device when the
- * context has one.  p = NULL selects the defaults listed above. */
+ * an affinity measure, Sec. 3.1).  The affinity, Galerkin and renumbering
+ * steps run on the GPU unless p->device is 0 or the context is host-only;
+ * the hierarchy is then uploaded for the solves.  p = NULL selects the
+ * defaults listed above. */
 int cfc_hierarchy_build(cfc_graph* g, const cfc_setup_params* p);
 /* Inspect level `level` of the host hierarchy. */
 int cfc_hierarchy_level(const cfc_graph* g, int32_t level, cfc_level_view* out);
@@ -244,10 +246,14 @@ int cfc_hierarchy_level(const cfc_graph* g, int32_t level, cfc_level_view* out);
 /* ---- solves --------------------------------------------------------------- */
 
 /* Solve L X = B (Eq. 1).  B, X: float64, column-major n x nrhs (column j at
- * B + j*n), host or device.  Each column must sum to zero within
- * 1e-12 * ||b||_1 (else CFC_E_INVALID).  X is returned mean-zero (= L^+ B).
- * Returns CFC_E_NOT_CONVERGED if any column missed p->tol (X still holds the
- * last iterate).  col_status: int32[nrhs] or NULL.  p, st may be NULL. */
+ * B + j*n), host or device (a host buffer costs one copy of each column
+ * block over PCIe each way).  Each column must be finite and sum to zero
+ * within 1e-12 * ||b||_1, else CFC_E_INVALID; columns are taken in blocks of
+ * the solve width, and the check of a block runs just before its solve, so
+ * on that error the columns of earlier blocks of X are already solved and
+ * the rest are untouched.  X is returned mean-zero (= L^+ B).  Returns
+ * CFC_E_NOT_CONVERGED if any column missed p->tol (X still holds the last
+ * iterate).  col_status: int32[nrhs] or NULL.  p, st may be NULL. */
 int cfc_solve(cfc_graph* g, int64_t nrhs, const double* B, double* X,
               const cfc_solve_params* p, cfc_solve_stats* st,
               int32_t* col_status);

@@ -11,6 +11,7 @@
 #include <fstream>
 #include <sstream>
 
+#include "block.hpp"
 #include "kern.hpp"
 #include "solver.hpp"
 
@@ -236,71 +237,57 @@ void solve_dense(Graph& g, int64_t nrhs, const double* B, double* X, const cfc_s
   check_params(p0);
   if (nrhs < 0 || (nrhs > 0 && (!B || !X))) fail(CFC_E_INVALID, "bad B/X");
   const int64_t n = g.n;
-  std::vector<double> hB;
-  const double* Bh = B;
-  const bool bdev = is_device_ptr(B), xdev = is_device_ptr(X);
-  if (bdev) {
-    hB.resize((size_t)n * nrhs);
-    CFC_HIP(hipMemcpy(hB.data(), B, hB.size() * sizeof(double), hipMemcpyDeviceToHost));
-    Bh = hB.data();
-  }
-  for (int64_t j = 0; j < nrhs; ++j) {
-    double s = 0, a = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      const double v = Bh[j * n + i];
-      if (!std::isfinite(v)) fail(CFC_E_INVALID, "B column " + std::to_string(j) + " is not finite");
-      s += v;
-      a += std::fabs(v);
-    }
-    if (std::fabs(s) > 1e-12 * a + 1e-300 && a > 0)
-      fail(CFC_E_INVALID, "B column " + std::to_string(j) + " does not sum to zero");
-  }
   cfc_solve_params p = tune_params(g, p0, nrhs);
   Solver S(g, p);
   Workspace& w = *S.ws;
   const int W = w.W;
   if (!w.rhs.p) w.rhs.alloc(g.ctx, (size_t)n * W * sizeof(double));
-  std::vector<double> blk((size_t)n * W), xo((size_t)n * W), hX;
-  double* Xh = X;
-  if (xdev) {
-    hX.resize((size_t)n * nrhs);
-    Xh = hX.data();
-  }
-  const std::vector<int32_t>& perm = g.H.perm;
+  // Column blocks of B and X are contiguous (column-major), so a host buffer
+  // moves as one copy per block through a device staging block; the
+  // transposes, the checks and the centring run on the device.
+  const bool bdev = is_device_ptr(B), xdev = is_device_ptr(X);
+  DBuf stage, part, stat;
+  if (!bdev || !xdev) stage.alloc(g.ctx, (size_t)n * W * sizeof(double));
+  part.alloc(g.ctx, (size_t)kColStatGrid * 2 * W * sizeof(double));
+  stat.alloc(g.ctx, 2 * (size_t)W * sizeof(double));
+  std::vector<double> hs(2 * (size_t)W);
+  const int* perm = g.D->perm.as<int>();
+  double* rhs = w.rhs.as<double>();
+  double* x64 = w.x64.as<double>();
+  double* sd = stage.as<double>();
   for (int64_t c0 = 0; c0 < nrhs; c0 += W) {
     const int nc = (int)std::min<int64_t>(W, nrhs - c0);
-    std::fill(blk.begin(), blk.end(), 0.0);
-    for (int j = 0; j < nc; ++j) {
-      const double* col = Bh + (c0 + j) * n;
-      for (int64_t i = 0; i < n; ++i) blk[(size_t)perm[i] * W + j] = col[i];
+    const double* Bc = B + c0 * n;
+    if (!bdev) {
+      CFC_HIP(hipMemcpyAsync(sd, Bc, (size_t)nc * n * sizeof(double), hipMemcpyHostToDevice, S.stream));
+      Bc = sd;
     }
-    CFC_HIP(hipMemcpyAsync(w.rhs.p, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice,
-                           S.stream));
-    RhsArgs r;
-    r.kind = 0;
-    r.dense = w.rhs.as<double>();
-    S.solve_block(r, nc, p, col_status ? col_status + c0 : nullptr, nullptr);
-    CFC_HIP(hipMemcpyAsync(xo.data(), w.x64.p, xo.size() * sizeof(double), hipMemcpyDeviceToHost,
+    block_in((int)n, W, nc, Bc, perm, rhs, S.stream);
+    col_stats((int)n, W, rhs, part.as<double>(), stat.as<double>(), S.stream);
+    CFC_HIP(hipMemcpyAsync(hs.data(), stat.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost,
                            S.stream));
     CFC_HIP(hipStreamSynchronize(S.stream));
     for (int j = 0; j < nc; ++j) {
-      double* col = Xh + (c0 + j) * n;
-      // mean-zero projection of the returned copy; compensated (Neumaier)
-      // summation keeps the mean accurate to FP64 rounding for large n
-      double sum = 0, comp = 0;
-      for (int64_t i = 0; i < n; ++i) {
-        const double v = xo[(size_t)perm[i] * W + j];
-        col[i] = v;
-        const double t = sum + v;
-        comp += std::fabs(sum) >= std::fabs(v) ? (sum - t) + v : (v - t) + sum;
-        sum = t;
-      }
-      const double m = (sum + comp) / double(n);
-      for (int64_t i = 0; i < n; ++i) col[i] -= m;
+      const double s = hs[j], a = hs[W + j];
+      if (!std::isfinite(a))
+        fail(CFC_E_INVALID, "B column " + std::to_string(c0 + j) + " is not finite");
+      if (std::fabs(s) > 1e-12 * a + 1e-300 && a > 0)
+        fail(CFC_E_INVALID, "B column " + std::to_string(c0 + j) + " does not sum to zero");
     }
+    RhsArgs r;
+    r.kind = 0;
+    r.dense = rhs;
+    S.solve_block(r, nc, p, col_status ? col_status + c0 : nullptr, nullptr);
+    // X = x - mean(x): the returned copy is exactly mean-zero up to rounding
+    col_stats((int)n, W, x64, part.as<double>(), stat.as<double>(), S.stream);
+    double* Xc = xdev ? X + c0 * n : sd;
+    block_out((int)n, W, nc, x64, perm, stat.as<double>(), Xc, S.stream);
+    if (!xdev)
+      CFC_HIP(hipMemcpyAsync(X + c0 * n, sd, (size_t)nc * n * sizeof(double), hipMemcpyDeviceToHost,
+                             S.stream));
+    CFC_HIP(hipStreamSynchronize(S.stream));
   }
   S.finish(st);
-  if (xdev) CFC_HIP(hipMemcpy(X, hX.data(), hX.size() * sizeof(double), hipMemcpyHostToDevice));
   if (S.converged < S.columns) fail(CFC_E_NOT_CONVERGED, "some columns missed the tolerance");
 }
 

@@ -121,6 +121,7 @@ struct DevHierarchy {
   DevLevel fwd;  // forward operator of an elimination level 0 (rows = kept rows)
   DBuf cpinv;   // n_c x n_c FP64
   DBuf iperm;   // level-0 row -> graph node (int32)
+  DBuf perm;    // graph node -> level-0 row (int32)
   DBuf wgraph;  // level-0 original weights FP64 per nnz (for JL RHS), = w64 unless unit
   int nc = 0;
   uint64_t bytes = 0;

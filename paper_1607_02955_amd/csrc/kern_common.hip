@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include "block.hpp"
 #include "kern.hpp"
 
 namespace cfc {
@@ -151,6 +152,87 @@ __global__ void k_gather_rc(int64_t q, const double* __restrict__ src, int W,
   if (i < q) out[i] = src[(size_t)row[i] * W + col[i]];
 }
 
+// Compensated (Neumaier) summation step: s + c carries the running sum to
+// about one rounding of the exact value.
+__device__ inline void neumaier_add(double& s, double& c, double v) {
+  const double t = s + v;
+  c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+  s = t;
+}
+
+// Column-major block (column j of nc at Bc + j n, graph node order) to the
+// node-major n x W layout in level-0 row order: rhs[perm[v] W + j]; columns
+// nc..W-1 are zero.  32 x 32 tiles staged in LDS so that both the column
+// reads (along v) and the row writes (along j) are contiguous.
+__global__ __launch_bounds__(256) void k_block_in(int n, int W, int nc, const double* __restrict__ Bc,
+                                                  const int* __restrict__ perm,
+                                                  double* __restrict__ rhs) {
+  __shared__ double tile[32][33];
+  const int v0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int k = ty; k < 32; k += 8) {
+    const int j = j0 + k, v = v0 + tx;
+    tile[k][tx] = (j < nc && v < n) ? Bc[(size_t)j * n + v] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int v = v0 + k, j = j0 + tx;
+    if (v < n && j < W) rhs[(size_t)perm[v] * W + j] = tile[tx][k];
+  }
+}
+
+// The inverse: Xc[j n + v] = x[perm[v] W + j] - cs[j] / n for j < nc (the
+// column sums cs of x, so the result is mean-zero).
+__global__ __launch_bounds__(256) void k_block_out(int n, int W, int nc, const double* __restrict__ x,
+                                                   const int* __restrict__ perm,
+                                                   const double* __restrict__ cs,
+                                                   double* __restrict__ Xc) {
+  __shared__ double tile[32][33];
+  const int v0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int k = ty; k < 32; k += 8) {
+    const int v = v0 + k, j = j0 + tx;
+    tile[k][tx] = (v < n && j < nc) ? x[(size_t)perm[v] * W + j] : 0.0;
+  }
+  __syncthreads();
+  const double inv = 1.0 / double(n);
+  for (int k = ty; k < 32; k += 8) {
+    const int j = j0 + k, v = v0 + tx;
+    if (j < nc && v < n) Xc[(size_t)j * n + v] = tile[tx][k] - cs[j] * inv;
+  }
+}
+
+// Per-column sum and sum of magnitudes of a node-major n x W block: each
+// workgroup adds a contiguous row range in order (partials [blk][2W]), then
+// one thread per column adds the partials in order.
+__global__ __launch_bounds__(256) void k_colstat_part(int n, int W, const double* __restrict__ x,
+                                                      double* __restrict__ part) {
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
+    double s = 0, c = 0, a = 0;
+    for (int r = r0; r < r1; ++r) {
+      const double v = x[(size_t)r * W + j];
+      neumaier_add(s, c, v);
+      a += fabs(v);
+    }
+    part[(size_t)blockIdx.x * 2 * W + j] = s + c;
+    part[(size_t)blockIdx.x * 2 * W + W + j] = a;
+  }
+}
+
+__global__ void k_colstat_final(int G, int W, const double* __restrict__ part, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= W) return;
+  double s = 0, c = 0, a = 0;
+  for (int g = 0; g < G; ++g) {
+    neumaier_add(s, c, part[(size_t)g * 2 * W + j]);
+    a += part[(size_t)g * 2 * W + W + j];
+  }
+  out[j] = s + c;
+  out[W + j] = a;
+}
+
 __global__ __launch_bounds__(256) void k_reduce_part(int n, const double* __restrict__ x,
                                                      double* __restrict__ part) {
   __shared__ double red[256];
@@ -226,6 +308,26 @@ void gather_rc(int64_t q, const double* src, int W, const int* row, const int* c
   if (q <= 0) return;
   hipLaunchKernelGGL(k_gather_rc, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, q, src, W, row,
                      col, out);
+}
+
+void block_in(int n, int W, int nc, const double* Bc, const int* perm, double* rhs, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_block_in, dim3((n + 31) / 32, (W + 31) / 32), dim3(256), 0, s, n, W, nc, Bc, perm,
+                     rhs);
+}
+
+void block_out(int n, int W, int nc, const double* x, const int* perm, const double* cs, double* Xc,
+               hipStream_t s) {
+  if (n <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(k_block_out, dim3((n + 31) / 32, (nc + 31) / 32), dim3(256), 0, s, n, W, nc, x,
+                     perm, cs, Xc);
+}
+
+void col_stats(int n, int W, const double* x, double* part, double* out, hipStream_t s) {
+  const int G = kColStatGrid;
+  hipLaunchKernelGGL(k_colstat_part, dim3(G), dim3(256), 0, s, n, W, x, part);
+  hipLaunchKernelGGL(k_colstat_final, dim3((W + 255) / 256), dim3(256), 0, s, G, W, (const double*)part,
+                     out);
 }
 
 void reduce_sum(int n, const double* x, double* part, double* out, hipStream_t s) {

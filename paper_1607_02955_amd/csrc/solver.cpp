@@ -176,7 +176,8 @@ void upload_hierarchy(Graph& g) {
   upload(c, D->cpinv, P, s);
   D->nc = nc;
   upload(c, D->iperm, H.iperm, s);
-  D->bytes += D->cpinv.bytes + D->iperm.bytes;
+  upload(c, D->perm, H.perm, s);
+  D->bytes += D->cpinv.bytes + D->iperm.bytes + D->perm.bytes;
   CFC_HIP(hipStreamSynchronize(s));
   g.ws.clear();
   g.D = std::move(D);

@@ -239,6 +239,35 @@ def test_graph_replay_matches_eager(ctx, W, depth):
         np.testing.assert_allclose(r_g, Rm[s, t], rtol=10 * tol, atol=1e-12)
 
 
+@pytest.mark.parametrize("device", [False, True])
+def test_solve_dense_blocks_and_checks(ctx, device):
+    """Several column blocks with a ragged tail, host or device buffers; a
+    column that is not finite or does not sum to zero is rejected."""
+    import torch
+    import paper_1607_02955_amd as cfc
+    eg = synth.random_connected(1500, 4500, seed=17)
+    g = load(ctx, eg, coarsest_max=64)
+    Lp, _ = dense_R(eg)
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((75, eg.n)) * rng.uniform(0.1, 100, (75, 1))
+    B -= B.mean(axis=1, keepdims=True)
+    want = (Lp @ B.T).T
+    wrap = (lambda a: torch.tensor(a, device="cuda")) if device else (lambda a: a)
+    unwrap = (lambda t: t.cpu().numpy()) if device else (lambda t: t)
+    X = unwrap(g.solve(wrap(B), tol=1e-9, block=32))
+    np.testing.assert_allclose(X, want, atol=1e-8 * np.abs(want).max())
+    assert np.all(np.abs(X.sum(axis=1)) <= 1e-12 * np.abs(X).sum(axis=1))
+    for bad in (np.nan, np.inf):
+        Bb = B.copy()
+        Bb[40, 7] = bad
+        with pytest.raises(cfc.CfcError, match="not finite"):
+            g.solve(wrap(Bb), tol=1e-9, block=32)
+    Bb = B.copy()
+    Bb[74, 3] += 1e-6 * np.abs(Bb[74]).sum()
+    with pytest.raises(cfc.CfcError, match="sum to zero"):
+        g.solve(wrap(Bb), tol=1e-9, block=32)
+
+
 def test_edge_cases(ctx):
     import paper_1607_02955_amd as cfc
     g1 = cfc.Graph(ctx, 1, [], [])
