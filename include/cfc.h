@@ -138,7 +138,14 @@ typedef struct {
 
 typedef struct {
   double tol;            /* per-column relative residual target (1e-6) */
-  int32_t precision;     /* CFC_PREC_MIXED (default) or CFC_PREC_FP64 */
+  int32_t precision;     /* CFC_PREC_MIXED (default) or CFC_PREC_FP64.  In
+                            CFC_PREC_MIXED with a one-Jacobi-step
+                            preconditioner (depth one, or an elimination
+                            level plus one step), z = M^-1 r is rounded to
+                            bfloat16 where it is formed, which halves the
+                            rows the operator product gathers; the FP64
+                            residual still certifies tol.  The environment
+                            variable CFC_BF16_Z=0 keeps z in FP32. */
   int32_t block;         /* right-hand sides per block W in {1,32,64,128,256,512};
                             0 = autotuned for the graph */
   int32_t max_refine;    /* FP64 refinement steps (20) */

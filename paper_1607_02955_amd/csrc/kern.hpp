@@ -64,7 +64,9 @@ struct KernTable {
   // workgroups per column slice (= rows of partial sums) of a kernel over
   // `units` units of the level
   int (*rows_grid)(const LevelArgs&, int units);
-  // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q
+  // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q.
+  // jac = 1: z is passed as r and formed as S r on the fly; jac = 2: z is
+  // its bfloat16 copy (uint16[n][W]).
   void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, const double* scal,
                   int first, double* part, int jac, hipStream_t);
   // Level-0 update and pre-smooth/residual/restrict:
@@ -78,13 +80,15 @@ struct KernTable {
   // Prolong + post-smooth: xt = S b + mu xc[agg], x = xt + S (b - L xt); partial b.x if part
   void (*prolong_smooth)(const LevelArgs&, const void* b, const void* xc, void* x,
                          double* part_rz, hipStream_t);
-  // x = S b (Jacobi step from zero) on a level; partial b.x if part
-  void (*jacobi)(const LevelArgs&, const void* b, void* x, double* part, hipStream_t);
+  // x = S b (Jacobi step from zero) on a level; partial b.x if part; bf = 1
+  // stores x as bfloat16 (requires part)
+  void (*jacobi)(const LevelArgs&, const void* b, void* x, double* part, int bf, hipStream_t);
   // Jacobi-PCG update on level 0: r_out = r_in - alpha q, x += alpha p,
-  // z = S r_out; partials |r_out|^2, sum x, r_out.z
+  // z = S r_out; partials |r_out|^2, sum x, r_out.z; bf = 1 stores z as
+  // bfloat16 (z non-null)
   void (*update_jacobi)(const LevelArgs&, const void* r_in, const void* q, const void* p, void* x,
                         void* r_out, void* z, const double* scal, int first, double* prr,
-                        double* pcs, double* prz, hipStream_t);
+                        double* pcs, double* prz, int bf, hipStream_t);
   // Coarsest solve x = Lc^+ b (FP64 arithmetic); Lc^+ is nc_pad x nc_pad.
   void (*coarse)(int nc, int nc_pad, const double* pinv, const void* b, void* x, hipStream_t);
   // Partial dots b.x over n rows (for the single-level case).
@@ -105,14 +109,16 @@ struct KernTable {
   void (*zero)(void* p, size_t bytes, hipStream_t);
   // Elimination level, forward step over the kept rows (lf = the forward
   // operator, lf.n = kept rows): t = r + F r.  jac = 0 writes t to out;
-  // jac = 1 writes z = sd1 * t and partial sums of r . z (grid rows_grid).
+  // jac = 1 writes z = sd1 * t and partial sums of r . z (grid rows_grid);
+  // jac = 2 does the same with z stored as bfloat16.
   void (*elim_fwd)(const LevelArgs& lf, const void* r, void* out, const void* sd1, double* part_rz,
                    int jac, hipStream_t);
   // Elimination level, back substitution z_f = (r_f + sum_c w_fc z_c) / D_ff
   // for the eliminated rows, with partial sums of r . z over the eliminated
   // rows (allrows = 0) or over all rows (allrows = 1); grid = elim_grid.
+  // bf = 1: z is held as bfloat16.
   void (*elim_back)(const LevelArgs& l0, const void* r, void* z, double* part_rz, int allrows,
-                    hipStream_t);
+                    int bf, hipStream_t);
   int (*elim_grid)(int units);
   // tp[u] += node throughput of the block's unit flows ps[j] -> pt[j] (rows,
   // -1 = unused column) summed over its first ncols columns; seg_part holds

@@ -69,6 +69,29 @@ __device__ __forceinline__ void st(T* p, const Vec<T, V>& x) {
   *reinterpret_cast<Vec<T, V>*>(p) = x;
 }
 
+// bfloat16 storage of the preconditioned residual z = S r on the depth-one
+// path: z is rounded once (to nearest, ties to even) where it is formed, and
+// that rounded z is what every later use sees (its own row, its
+// neighbours' gathers, r.z), so the CG recurrences stay consistent
+// (q = L p holds to FP32 rounding) while the gathered rows are half as wide.
+typedef unsigned short bf16_t;
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ld_bf(const bf16_t* p) {
+  const Vec<bf16_t, V> h = ld<bf16_t, V>(p);
+  Vec<T, V> r;
+#pragma unroll
+  for (int i = 0; i < V; ++i) r.v[i] = T(bf2f(h.v[i]));
+  return r;
+}
+
 // Streaming (non-temporal) row access for values read or written once per
 // kernel: they should not displace the rows that neighbours gather again.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -219,7 +242,9 @@ __device__ __forceinline__ void add_heavy(const LevelArgs& L, int u, T* nb, int 
 // Heavy-row pre-pass: one workgroup per (segment, column slice); its row
 // groups split the segment's edges and row group 0 stores the sum
 // hpart[seg] = sum_e w_e f(col_e) with f chosen by KIND.
-enum HeavyKind { HK_SPMM = 0, HK_RESTRICT = 1, HK_RESTRICT_UPD = 2, HK_PROLONG = 3, HK_RES64 = 4 };
+enum HeavyKind {
+  HK_SPMM = 0, HK_RESTRICT = 1, HK_RESTRICT_UPD = 2, HK_PROLONG = 3, HK_RES64 = 4, HK_BF16 = 5
+};
 
 template <typename T, int W, int KIND>
 __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restrict__ a,
@@ -241,6 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
 #pragma unroll
     for (int i = 0; i < V; ++i) nb[i] = 0;
     gather_acc<T, W>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
+      if constexpr (KIND == HK_BF16)
+        return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(a) + (size_t)v * W + c0);
       Vec<T, V> r = ld<T, V>(a + (size_t)v * W + c0);
       if constexpr (KIND == HK_RESTRICT || KIND == HK_RESTRICT_UPD) {
         if constexpr (KIND == HK_RESTRICT_UPD) {
@@ -271,9 +298,10 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
 
 // ---------------------------------------------------------------------------
 // PCG step on level 0: q = L z + beta q, p = z + beta p; partial p.q.
-// JAC: the preconditioner is one Jacobi step, and z = S r is formed on the
-// fly from the residual passed in place of z (saves storing z).
-template <typename T, int W, bool JAC, int SPLIT>
+// JAC = 1: the preconditioner is one Jacobi step, and z = S r is formed on
+// the fly from the residual passed in place of z (saves storing z).
+// JAC = 2: z is passed as its bfloat16 copy (bf16_t[n][W]).
+template <typename T, int W, int JAC, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __restrict__ z,
                                                     T* __restrict__ p, T* __restrict__ q,
                                                     const double* __restrict__ scal, int first,
@@ -304,8 +332,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
     for (int i = 0; i < V; ++i) nb[i] = 0;
     if (u < L.n)
       gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT, [&](int v) {
+        if constexpr (JAC == 2)
+          return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(z) + (size_t)v * W + c0);
         Vec<T, V> zv = ld<T, V>(z + (size_t)v * W + c0);
-        if constexpr (JAC) {
+        if constexpr (JAC == 1) {
           const T f = sd[v];
 #pragma unroll
           for (int i = 0; i < V; ++i) zv.v[i] *= f;
@@ -316,8 +346,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
     if (u < L.n && D::leader(rg)) {
       add_heavy<T, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
-      Vec<T, V> zu = ld<T, V>(z + o);
-      if constexpr (JAC) {
+      Vec<T, V> zu;
+      if constexpr (JAC == 2)
+        zu = ld_bf<T, V>(reinterpret_cast<const bf16_t*>(z) + o);
+      else
+        zu = ld<T, V>(z + o);
+      if constexpr (JAC == 1) {
         const T f = sd[u];
 #pragma unroll
         for (int i = 0; i < V; ++i) zu.v[i] *= f;
@@ -499,9 +533,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
 // ---------------------------------------------------------------------------
 // Smoother-only "solve" on the deepest level a truncated V-cycle uses:
 // x = S b (one Jacobi step from zero, S = omega D^-1); partial b.x if part.
-template <typename T, int W, bool DOT>
+// BF: x is stored as bfloat16 (bf16_t[n][W]) and the partial uses the
+// rounded values.
+template <typename T, int W, bool DOT, bool BF>
 __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restrict__ b,
-                                                   T* __restrict__ x, double* __restrict__ part) {
+                                                   void* __restrict__ xv, double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   __shared__ double lds[DOT ? RG * WS : 1];
   int slice, rb, grb;
@@ -520,24 +556,33 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
     const Vec<T, V> bu = ld<T, V>(b + o);
     const T su = sd[u];
     Vec<T, V> xo;
+    Vec<bf16_t, V> xh;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       xo.v[i] = su * bu.v[i];
+      if constexpr (BF) {
+        xh.v[i] = f2bf(float(xo.v[i]));
+        xo.v[i] = T(bf2f(xh.v[i]));
+      }
       if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
     }
-    if (x) st<T, V>(x + o, xo);
+    if constexpr (BF)
+      st<bf16_t, V>(static_cast<bf16_t*>(xv) + o, xh);
+    else if (xv)
+      st<T, V>(static_cast<T*>(xv) + o, xo);
   }
   if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // Jacobi-preconditioned CG update on level 0 (a V-cycle of depth one):
 // r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, z = S r_out;
-// partials |r_out|^2, sum x, r_out . z.
-template <typename T, int W>
+// partials |r_out|^2, sum x, r_out . z.  BF: z is stored (non-null) as
+// bfloat16 and r_out . z uses the rounded z.
+template <typename T, int W, bool BF>
 __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* __restrict__ r_in,
                                                           const T* __restrict__ q, const T* __restrict__ p,
                                                           T* __restrict__ x, T* __restrict__ r_out,
-                                                          T* __restrict__ z, const double* __restrict__ scal,
+                                                          void* __restrict__ z, const double* __restrict__ scal,
                                                           int first, double* __restrict__ part_rr,
                                                           double* __restrict__ part_cs,
                                                           double* __restrict__ part_rz) {
@@ -563,6 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     Vec<T, V> rn = ld_nt<T, V>(r_in + o);
     const Vec<T, V> qu = ld_nt<T, V>(q + o), pu = ld_nt<T, V>(p + o);
     Vec<T, V> xu, zu;
+    Vec<bf16_t, V> zh;
     if (!first) xu = ld_nt<T, V>(x + o);
     const T su = sd[u];
 #pragma unroll
@@ -570,13 +616,20 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
       rn.v[i] -= alpha[i] * qu.v[i];
       xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
       zu.v[i] = su * rn.v[i];
+      if constexpr (BF) {
+        zh.v[i] = f2bf(float(zu.v[i]));
+        zu.v[i] = T(bf2f(zh.v[i]));
+      }
       rr[i] += double(rn.v[i]) * double(rn.v[i]);
       cs[i] += double(xu.v[i]);
       rz[i] += double(rn.v[i]) * double(zu.v[i]);
     }
     st_nt<T, V>(x + o, xu);
     st_nt<T, V>(r_out + o, rn);
-    if (z) st<T, V>(z + o, zu);
+    if constexpr (BF)
+      st<bf16_t, V>(static_cast<bf16_t*>(z) + o, zh);
+    else if (z)
+      st<T, V>(static_cast<T*>(z) + o, zu);
   }
   block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
   block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
@@ -870,9 +923,11 @@ __global__ __launch_bounds__(kBlock) void k_jl_rowdot(int n, const double* __res
 
 // t = r + F r over the kept rows (F = the forward operator); with JAC the
 // next level is smoothed once in place: out = sd1 * t, partial sums r . out.
-template <typename T, int W, bool JAC>
+// BF (with JAC): out is stored as bfloat16 and the partials use the rounded
+// values.
+template <typename T, int W, bool JAC, bool BF>
 __global__ __launch_bounds__(kBlock) void k_elim_fwd(LevelArgs F, const T* __restrict__ r,
-                                                     T* __restrict__ out, const T* __restrict__ sd1,
+                                                     void* __restrict__ out, const T* __restrict__ sd1,
                                                      double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   __shared__ double lds[JAC ? RG * WS : 1];
@@ -897,27 +952,37 @@ __global__ __launch_bounds__(kBlock) void k_elim_fwd(LevelArgs F, const T* __res
     const size_t o = (size_t)u * W + c0;
     const Vec<T, V> ru = ld<T, V>(r + o);
     Vec<T, V> ov;
+    Vec<bf16_t, V> oh;
     if constexpr (JAC) {
       const T su = sd1[u];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         ov.v[i] = su * (ru.v[i] + nb[i]);
+        if constexpr (BF) {
+          oh.v[i] = f2bf(float(ov.v[i]));
+          ov.v[i] = T(bf2f(oh.v[i]));
+        }
         acc[i] += double(ru.v[i]) * double(ov.v[i]);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < V; ++i) ov.v[i] = ru.v[i] + nb[i];
     }
-    st<T, V>(out + o, ov);
+    if constexpr (BF)
+      st<bf16_t, V>(static_cast<bf16_t*>(out) + o, oh);
+    else
+      st<T, V>(static_cast<T*>(out) + o, ov);
   }
   if constexpr (JAC) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // z_f for the eliminated rows, then partial sums of r . z over the eliminated
-// rows (ALL = false) or over every row (ALL = true).
-template <typename T, int W, bool ALL>
+// rows (ALL = false) or over every row (ALL = true).  BF: z is held as
+// bfloat16 (the kept rows' z_c read as stored, z_f rounded when stored and
+// in the partials).
+template <typename T, int W, bool ALL, bool BF>
 __global__ __launch_bounds__(kBlock) void k_elim_back(LevelArgs L, const T* __restrict__ r,
-                                                      T* __restrict__ z, double* __restrict__ part) {
+                                                      void* __restrict__ zv, double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   __shared__ double lds[RG * WS];
   int slice, rb, grb;
@@ -925,6 +990,14 @@ __global__ __launch_bounds__(kBlock) void k_elim_back(LevelArgs L, const T* __re
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* ew = static_cast<const T*>(L.ew);
   const T* einv = static_cast<const T*>(L.einv);
+  T* z = static_cast<T*>(zv);
+  bf16_t* zh = static_cast<bf16_t*>(zv);
+  auto zrow = [&](int a) {
+    if constexpr (BF)
+      return ld_bf<T, V>(zh + (size_t)a * W + c0);
+    else
+      return ld<T, V>(z + (size_t)a * W + c0);
+  };
   const int base = ALL ? 0 : L.nC;
   double acc[V];
 #pragma unroll
@@ -941,20 +1014,30 @@ __global__ __launch_bounds__(kBlock) void k_elim_back(LevelArgs L, const T* __re
       const int i = u - L.nC;
       const int a = L.enb[2 * i], b = L.enb[2 * i + 1];
       const T wa = ew[2 * i], di = einv[i];
-      const Vec<T, V> za = ld<T, V>(z + (size_t)a * W + c0);
+      const Vec<T, V> za = zrow(a);
 #pragma unroll
       for (int k = 0; k < V; ++k) zu.v[k] = ru.v[k] + wa * za.v[k];
       if (b >= 0) {
         const T wb = ew[2 * i + 1];
-        const Vec<T, V> zb = ld<T, V>(z + (size_t)b * W + c0);
+        const Vec<T, V> zb = zrow(b);
 #pragma unroll
         for (int k = 0; k < V; ++k) zu.v[k] += wb * zb.v[k];
       }
 #pragma unroll
       for (int k = 0; k < V; ++k) zu.v[k] *= di;
-      st<T, V>(z + o, zu);
+      if constexpr (BF) {
+        Vec<bf16_t, V> h;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          h.v[k] = f2bf(float(zu.v[k]));
+          zu.v[k] = T(bf2f(h.v[k]));
+        }
+        st<bf16_t, V>(zh + o, h);
+      } else {
+        st<T, V>(z + o, zu);
+      }
     } else {
-      zu = ld<T, V>(z + o);
+      zu = zrow(u);
     }
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] += double(ru.v[k]) * double(zu.v[k]);
@@ -1165,12 +1248,15 @@ struct Launch {
   static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, const double* scal,
                       int first, double* part, int jac, hipStream_t s) {
 #define ARGS L, (const T*)z, (T*)p, (T*)q, scal, first, part
-    if (jac) {
+    if (jac == 2) {
+      heavy<HK_BF16>(L, z, nullptr, nullptr, scal, s);
+      CFC_LAUNCH(k_spmm_pq, L.n, T, W, 2);
+    } else if (jac) {
       heavy<HK_RESTRICT>(L, z, nullptr, nullptr, scal, s);  // sum of w_e sd_v r_v
-      CFC_LAUNCH(k_spmm_pq, L.n, T, W, true);
+      CFC_LAUNCH(k_spmm_pq, L.n, T, W, 1);
     } else {
       heavy<HK_SPMM>(L, z, nullptr, nullptr, scal, s);
-      CFC_LAUNCH(k_spmm_pq, L.n, T, W, false);
+      CFC_LAUNCH(k_spmm_pq, L.n, T, W, 0);
     }
 #undef ARGS
   }
@@ -1206,23 +1292,32 @@ struct Launch {
       CFC_LAUNCH(k_prolong_smooth, L.n, T, W, false);
 #undef ARGS
   }
-  static void jacobi(const LevelArgs& L, const void* b, void* x, double* part, hipStream_t s) {
+  static void jacobi(const LevelArgs& L, const void* b, void* x, double* part, int bf, hipStream_t s) {
     const int g = grid_units(L.n, RG);
     if (!g) return;
-    if (part)
-      hipLaunchKernelGGL((k_jacobi<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)b,
-                         (T*)x, part);
+    if (bf && part)
+      hipLaunchKernelGGL((k_jacobi<T, W, true, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)b, x, part);
+    else if (part)
+      hipLaunchKernelGGL((k_jacobi<T, W, true, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)b, x, part);
     else
-      hipLaunchKernelGGL((k_jacobi<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)b,
-                         (T*)x, part);
+      hipLaunchKernelGGL((k_jacobi<T, W, false, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)b, x, part);
   }
   static void update_jacobi(const LevelArgs& L, const void* r_in, const void* q, const void* p,
                             void* x, void* r_out, void* z, const double* scal, int first,
-                            double* prr, double* pcs, double* prz, hipStream_t s) {
+                            double* prr, double* pcs, double* prz, int bf, hipStream_t s) {
     const int g = grid_units(L.n, RG);
     if (!g) return;
-    hipLaunchKernelGGL((k_update_jacobi<T, W>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r_in,
-                       (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)z, scal, first, prr, pcs, prz);
+    if (bf)
+      hipLaunchKernelGGL((k_update_jacobi<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first,
+                         prr, pcs, prz);
+    else
+      hipLaunchKernelGGL((k_update_jacobi<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first,
+                         prr, pcs, prz);
   }
   static void coarse(int nc, int ncp, const double* A, const void* b, void* x, hipStream_t s) {
 #ifndef CFC_COARSE_NO_MFMA
@@ -1289,23 +1384,32 @@ struct Launch {
     heavy<HK_SPMM>(L, r, nullptr, nullptr, nullptr, s);
     const int g = elim_grid(L.n);
     if (!g) return;
-    if (jac)
-      hipLaunchKernelGGL((k_elim_fwd<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
-                         (T*)out, (const T*)sd1, part);
+    if (jac == 2)
+      hipLaunchKernelGGL((k_elim_fwd<T, W, true, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, out, (const T*)sd1, part);
+    else if (jac)
+      hipLaunchKernelGGL((k_elim_fwd<T, W, true, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, out, (const T*)sd1, part);
     else
-      hipLaunchKernelGGL((k_elim_fwd<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
-                         (T*)out, (const T*)sd1, part);
+      hipLaunchKernelGGL((k_elim_fwd<T, W, false, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, out, (const T*)sd1, part);
   }
   static void elim_back(const LevelArgs& L, const void* r, void* z, double* part, int allrows,
-                        hipStream_t s) {
+                        int bf, hipStream_t s) {
     const int g = elim_grid(allrows ? L.n : L.n - L.nC);
     if (!g) return;
-    if (allrows)
-      hipLaunchKernelGGL((k_elim_back<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
-                         (T*)z, part);
+    if (allrows && bf)
+      hipLaunchKernelGGL((k_elim_back<T, W, true, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, z, part);
+    else if (allrows)
+      hipLaunchKernelGGL((k_elim_back<T, W, true, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, z, part);
+    else if (bf)
+      hipLaunchKernelGGL((k_elim_back<T, W, false, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, z, part);
     else
-      hipLaunchKernelGGL((k_elim_back<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r,
-                         (T*)z, part);
+      hipLaunchKernelGGL((k_elim_back<T, W, false, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)r, z, part);
   }
   static void throughput(const LevelArgs& L, const double* x64, int ncols, const int* ps,
                          const int* pt, double* seg_part, double* tp, hipStream_t s) {

@@ -345,15 +345,17 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     // depth one: Jacobi-preconditioned CG, z = S r
     if (update) {
       prof_begin(K_RESTRICT0);
-      k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
-                      w.part_ptr(P_RR), w.part_ptr(P_CS), w.part_ptr(P_RZ), s);
-      const double ub = d0.n * nw * (first_x ? 5 : 6) + 2.0 * es * d0.n;
+      k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, bfz ? w.z.p : nullptr,
+                      w.scal.as<double>(), first_x, w.part_ptr(P_RR), w.part_ptr(P_CS),
+                      w.part_ptr(P_RZ), bfz ? 1 : 0, s);
+      const double ub = d0.n * nw * (first_x ? 5 : 6) + 2.0 * es * d0.n + (bfz ? 2.0 * d0.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
       g_rr = g_cs = grid_for(d0.n, k.rg);
     } else {
-      k.jacobi(w.la[0], r_in, nullptr, w.part_ptr(P_RZ), s);  // r . S r only
-      bytes += d0.n * nw + es * d0.n;
+      // r . S r (and the bfloat16 copy of z = S r when the product gathers it)
+      k.jacobi(w.la[0], r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), bfz ? 1 : 0, s);
+      bytes += d0.n * nw + es * d0.n + (bfz ? 2.0 * d0.n * w.W : 0.0);
     }
     g_rz = grid_for(d0.n, k.rg);
     return;
@@ -398,7 +400,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     bytes += 2.0 * nc * nw + 8.0 * nc * nc;
   } else {
     const DevLevel& d = g->D->lv[L - 1];
-    k.jacobi(w.la[L - 1], w.b[L - 1].p, w.xl[L - 1].p, nullptr, s);
+    k.jacobi(w.la[L - 1], w.b[L - 1].p, w.xl[L - 1].p, nullptr, 0, s);
     bytes += 2.0 * d.n * nw + es * d.n;
   }
   for (int l = L - 2; l >= 1; --l) {
@@ -443,12 +445,15 @@ void Solver::vcycle_elim(bool update, bool first_x, const void* r_in, void* r_ou
   const double fb = 2.0 * nc * nw + (double)(n - nc) * nw + 8.0 * fw.nnz + 4.0 * nc;
   const double bb = (double)(n - nc) * nw * 2 + 2.0 * (n - nc) * nw + 16.0 * (n - nc);
   if (L == 2 && !exact) {
-    // Schur complement smoothed once: z_C = S t_C, fused into the forward step
-    k.elim_fwd(w.lf, rsrc, w.z.p, w.la[1].sd, w.part_ptr(P_RZ), 1, s);
+    // Schur complement smoothed once: z_C = S t_C, fused into the forward
+    // step (z in bfloat16 when the product gathers it so)
+    k.elim_fwd(w.lf, rsrc, w.z.p, w.la[1].sd, w.part_ptr(P_RZ), bfz ? 2 : 1, s);
     const int g1 = k.elim_grid(nc);
-    k.elim_back(w.la[0], rsrc, w.z.p, w.part_ptr(P_RZ) + (size_t)g1 * w.W, 0, s);
+    k.elim_back(w.la[0], rsrc, w.z.p, w.part_ptr(P_RZ) + (size_t)g1 * w.W, 0, bfz ? 1 : 0, s);
     g_rz = g1 + k.elim_grid(n - nc);
-    bytes += fb + bb;
+    // a bfloat16 z moves 2 bytes per value instead of es
+    const double zs = bfz ? (es - 2.0) * w.W : 0.0;
+    bytes += fb + bb - zs * (nc + 3.0 * (n - nc));
     return;
   }
   k.elim_fwd(w.lf, rsrc, w.b[1].p, nullptr, nullptr, 0, s);
@@ -465,7 +470,7 @@ void Solver::vcycle_elim(bool update, bool first_x, const void* r_in, void* r_ou
     bytes += 2.0 * ncs * nw + 8.0 * ncs * ncs;
   } else {
     const DevLevel& d = g->D->lv[L - 1];
-    k.jacobi(w.la[L - 1], w.b[L - 1].p, xl(L - 1), nullptr, s);
+    k.jacobi(w.la[L - 1], w.b[L - 1].p, xl(L - 1), nullptr, 0, s);
     bytes += 2.0 * d.n * nw + es * d.n;
   }
   for (int l = L - 2; l >= 1; --l) {
@@ -473,7 +478,7 @@ void Solver::vcycle_elim(bool update, bool first_x, const void* r_in, void* r_ou
     k.prolong_smooth(w.la[l], w.b[l].p, xl(l + 1), xl(l), nullptr, s);
     bytes += 2.0 * d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * d.n;
   }
-  k.elim_back(w.la[0], rsrc, w.z.p, w.part_ptr(P_RZ), 1, s);
+  k.elim_back(w.la[0], rsrc, w.z.p, w.part_ptr(P_RZ), 1, 0, s);
   g_rz = k.elim_grid(n);
   bytes += bb + 2.0 * nc * nw;
 }
@@ -534,10 +539,13 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
   const int W = w.W;
   prof_begin(K_SPMM);
   // depth one: z = S r_in is formed inside the product kernel
+  // (or gathered from its bfloat16 copy in ws.z)
   const bool jac = nuse == 1 && w.nlev > 1;
-  k.spmm_pq(w.la[0], jac ? r_in : w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first, w.part_ptr(P_PQ),
-            jac ? 1 : 0, stream);
-  const double sb = d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) + (jac ? es * d0.n : 0.0);
+  k.spmm_pq(w.la[0], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first,
+            w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
+  const double sb = bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
+                        : d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) +
+                              (jac ? es * d0.n : 0.0);
   prof_end(K_SPMM, sb);
   bytes += sb;
   finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
@@ -686,6 +694,14 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   profile = pe && pe[0] == '1';
   ws = &get_workspace(*g, p.block, p.precision == CFC_PREC_FP64, stream, mem);
   nuse = (p.levels >= 1 && p.levels <= ws->nlev) ? p.levels : ws->nlev;
+  // FP32 inner solves whose preconditioner is one Jacobi step on level 0
+  // (depth one) or an elimination level plus one Jacobi step on its Schur
+  // complement: keep z as bfloat16 for the product's gathers (CFC_BF16_Z=0
+  // keeps it FP32).
+  const char* bz = std::getenv("CFC_BF16_Z");
+  const bool jac1 = nuse == 1 && ws->nlev > 1;
+  const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && ws->nlev > 2;
+  bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
   CFC_HIP(hipEventCreate(&ev0));
   CFC_HIP(hipEventCreate(&ev1));
   CFC_HIP(hipEventRecord(ev0, stream));

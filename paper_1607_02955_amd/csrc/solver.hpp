@@ -46,6 +46,7 @@ struct Solver {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int g_rz = 0, g_rr = 0, g_cs = 0;
   int nuse = 1;  // V-cycle depth
+  bool bfz = false;  // depth one: z = S r stored as bfloat16 in ws->z
   // statistics
   int64_t columns = 0, converged = 0, inner_iters = 0, refine_steps = 0, blocks = 0;
   double max_rel = 0, bytes = 0;

@@ -336,6 +336,34 @@ def test_elimination_level_all_depths(ctx, W, prec):
     np.testing.assert_allclose(r_g, Rm[s, t], rtol=10 * tol, atol=1e-12)
 
 
+@pytest.mark.parametrize("case", ["depth1_hubs", "elim_depth2"])
+def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
+    """The bfloat16 copy of z = M^-1 r (depth one, or elimination plus one
+    Jacobi step) gives the oracle's resistances at the requested tolerance,
+    as the FP32 z does, in about as many iterations."""
+    if case == "depth1_hubs":
+        eg = synth.barabasi_albert(3000, 3, seed=44)  # hubs above the heavy-row threshold
+        g = load(ctx, eg, coarsest_max=64)
+        depth, W = 1, 256
+    else:
+        eg = leafy_graph(seed=45)
+        g = load(ctx, eg, coarsest_max=64, eliminate=2)
+        assert g.info()["eliminated"] > 0 and g.info()["levels"] >= 3
+        depth, W = 2, 64
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(9)
+    s = rng.integers(0, eg.n, 2 * W + 3)
+    t = rng.integers(0, eg.n, 2 * W + 3)
+    its = {}
+    for bz in ("0", "1"):
+        monkeypatch.setenv("CFC_BF16_Z", bz)
+        r, st = g.resistance(s, t, block=W, tol=1e-8, levels=depth, stats=True, max_inner=3000)
+        say("bf16 z", case, bz, st["inner_iters"], st["refine_steps"])
+        np.testing.assert_allclose(r, Rm[s, t], rtol=1e-7, atol=1e-12)
+        its[bz] = st["inner_iters"]
+    assert its["1"] <= 1.1 * its["0"] + 3
+
+
 def test_elimination_to_two_nodes_is_exact(ctx):
     """A star loses every leaf but one: the elimination level over a two-node
     coarsest level is an exact solver."""
