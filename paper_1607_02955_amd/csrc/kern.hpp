@@ -66,8 +66,9 @@ struct KernTable {
   int (*rows_grid)(const LevelArgs&, int units);
   // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q.
   // jac = 1: z is passed as r and formed as S r on the fly; jac = 2: z is
-  // its bfloat16 copy (uint16[n][W]).
-  void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, const double* scal,
+  // its bfloat16 copy (uint16[n][W]).  x (nullable): also apply the previous
+  // iteration's x += alpha p (not on the first iteration).
+  void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, void* x, const double* scal,
                   int first, double* part, int jac, hipStream_t);
   // Level-0 update and pre-smooth/residual/restrict:
   //   update: r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, partials |r_out|^2, sum x
@@ -85,10 +86,14 @@ struct KernTable {
   void (*jacobi)(const LevelArgs&, const void* b, void* x, double* part, int bf, hipStream_t);
   // Jacobi-PCG update on level 0: r_out = r_in - alpha q, x += alpha p,
   // z = S r_out; partials |r_out|^2, sum x, r_out.z; bf = 1 stores z as
-  // bfloat16 (z non-null)
+  // bfloat16 (z non-null); xf = 1 leaves x to spmm_pq (x = 0 on the first
+  // iteration, no sum-x partials) and does not read p
   void (*update_jacobi)(const LevelArgs&, const void* r_in, const void* q, const void* p, void* x,
                         void* r_out, void* z, const double* scal, int first, double* prr,
-                        double* pcs, double* prz, int bf, hipStream_t);
+                        double* pcs, double* prz, int bf, int xf, hipStream_t);
+  // x += alpha p over n level-0 rows, partial column sums of x (grid
+  // grid_for(n, rg)): the last update when spmm_pq carries them
+  void (*xfinal)(int n, void* x, const void* p, const double* scal, double* pcs, hipStream_t);
   // Coarsest solve x = Lc^+ b (FP64 arithmetic); Lc^+ is nc_pad x nc_pad.
   void (*coarse)(int nc, int nc_pad, const double* pinv, const void* b, void* x, hipStream_t);
   // Partial dots b.x over n rows (for the single-level case).

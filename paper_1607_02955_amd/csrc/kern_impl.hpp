@@ -301,9 +301,12 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
 // JAC = 1: the preconditioner is one Jacobi step, and z = S r is formed on
 // the fly from the residual passed in place of z (saves storing z).
 // JAC = 2: z is passed as its bfloat16 copy (bf16_t[n][W]).
+// x (nullable, depth one): the previous iteration's x += alpha p_old is
+// applied here, where p_old is read anyway, instead of in the update kernel.
 template <typename T, int W, int JAC, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __restrict__ z,
                                                     T* __restrict__ p, T* __restrict__ q,
+                                                    T* __restrict__ x,
                                                     const double* __restrict__ scal, int first,
                                                     double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
@@ -316,11 +319,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
   const T* w = static_cast<const T*>(L.w);
   const T* deg = static_cast<const T*>(L.deg);
   const T* sd = static_cast<const T*>(L.sd);
-  T beta[V];
+  const bool xf = x && !first;
+  T beta[V], alpha[V];
   double acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) {
     beta[i] = first ? T(0) : T(scal[S_BETA * W + c0 + i]);
+    alpha[i] = xf ? T(scal[S_ALPHA * W + c0 + i]) : T(0);
     acc[i] = 0;
   }
   int tb, te;
@@ -368,6 +373,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
         for (int i = 0; i < V; ++i) {
           pn.v[i] = zu.v[i] + beta[i] * po.v[i];
           qn.v[i] = (du * zu.v[i] - nb[i]) + beta[i] * qo.v[i];
+        }
+        if (xf) {
+          Vec<T, V> xo = ld_nt<T, V>(x + o);
+#pragma unroll
+          for (int i = 0; i < V; ++i) xo.v[i] += alpha[i] * po.v[i];
+          st_nt<T, V>(x + o, xo);
         }
       }
       st_nt<T, V>(p + o, pn);
@@ -577,7 +588,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
 // Jacobi-preconditioned CG update on level 0 (a V-cycle of depth one):
 // r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, z = S r_out;
 // partials |r_out|^2, sum x, r_out . z.  BF: z is stored (non-null) as
-// bfloat16 and r_out . z uses the rounded z.
+// bfloat16 and r_out . z uses the rounded z.  xf: x is updated by the
+// product kernel of the next iteration instead (this kernel reads neither x
+// nor p, writes x = 0 on the first iteration and no sum-x partials).
 template <typename T, int W, bool BF>
 __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* __restrict__ r_in,
                                                           const T* __restrict__ q, const T* __restrict__ p,
@@ -585,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
                                                           void* __restrict__ z, const double* __restrict__ scal,
                                                           int first, double* __restrict__ part_rr,
                                                           double* __restrict__ part_cs,
-                                                          double* __restrict__ part_rz) {
+                                                          double* __restrict__ part_rz, int xf) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   __shared__ double lds[RG * WS];
   int slice, rb, grb;
@@ -606,15 +619,21 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     if (u >= L.n) continue;
     const size_t o = (size_t)u * W + c0;
     Vec<T, V> rn = ld_nt<T, V>(r_in + o);
-    const Vec<T, V> qu = ld_nt<T, V>(q + o), pu = ld_nt<T, V>(p + o);
-    Vec<T, V> xu, zu;
+    const Vec<T, V> qu = ld_nt<T, V>(q + o);
+    Vec<T, V> xu, zu, pu;
     Vec<bf16_t, V> zh;
-    if (!first) xu = ld_nt<T, V>(x + o);
+    if (!xf) {
+      pu = ld_nt<T, V>(p + o);
+      if (!first) xu = ld_nt<T, V>(x + o);
+    }
     const T su = sd[u];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       rn.v[i] -= alpha[i] * qu.v[i];
-      xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
+      if (xf)
+        xu.v[i] = 0;
+      else
+        xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
       zu.v[i] = su * rn.v[i];
       if constexpr (BF) {
         zh.v[i] = f2bf(float(zu.v[i]));
@@ -624,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
       cs[i] += double(xu.v[i]);
       rz[i] += double(rn.v[i]) * double(zu.v[i]);
     }
-    st_nt<T, V>(x + o, xu);
+    if (!xf || first) st_nt<T, V>(x + o, xu);
     st_nt<T, V>(r_out + o, rn);
     if constexpr (BF)
       st<bf16_t, V>(static_cast<bf16_t*>(z) + o, zh);
@@ -632,8 +651,44 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
       st<T, V>(static_cast<T*>(z) + o, zu);
   }
   block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
-  block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
+  if (!xf) block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
   block_store<W>(rz, lds, part_rz + (size_t)rb * W + slice * WS);
+}
+
+// Last CG update of x when the product kernel carries the x updates:
+// x += alpha p; partial column sums of x.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_xfinal(int n, T* __restrict__ x, const T* __restrict__ p,
+                                                   const double* __restrict__ scal,
+                                                   double* __restrict__ part_cs) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[RG * WS];
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  T alpha[V];
+  double cs[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    alpha[i] = T(scal[S_ALPHA * W + c0 + i]);
+    cs[i] = 0;
+  }
+  int tb, te;
+  block_tiles((n + RG - 1) / RG, rb, grb, tb, te);
+  for (int t = tb; t < te; ++t) {
+    const int u = t * RG + rg;
+    if (u >= n) continue;
+    const size_t o = (size_t)u * W + c0;
+    Vec<T, V> xu = ld_nt<T, V>(x + o);
+    const Vec<T, V> pu = ld_nt<T, V>(p + o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      xu.v[i] += alpha[i] * pu.v[i];
+      cs[i] += double(xu.v[i]);
+    }
+    st_nt<T, V>(x + o, xu);
+  }
+  block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
 }
 
 // ---------------------------------------------------------------------------
@@ -1245,9 +1300,9 @@ struct Launch {
                        (const T*)q, (const T*)xc, scal);
   }
 
-  static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, const double* scal,
-                      int first, double* part, int jac, hipStream_t s) {
-#define ARGS L, (const T*)z, (T*)p, (T*)q, scal, first, part
+  static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, void* x,
+                      const double* scal, int first, double* part, int jac, hipStream_t s) {
+#define ARGS L, (const T*)z, (T*)p, (T*)q, (T*)x, scal, first, part
     if (jac == 2) {
       heavy<HK_BF16>(L, z, nullptr, nullptr, scal, s);
       CFC_LAUNCH(k_spmm_pq, L.n, T, W, 2);
@@ -1307,17 +1362,23 @@ struct Launch {
   }
   static void update_jacobi(const LevelArgs& L, const void* r_in, const void* q, const void* p,
                             void* x, void* r_out, void* z, const double* scal, int first,
-                            double* prr, double* pcs, double* prz, int bf, hipStream_t s) {
+                            double* prr, double* pcs, double* prz, int bf, int xf, hipStream_t s) {
     const int g = grid_units(L.n, RG);
     if (!g) return;
     if (bf)
       hipLaunchKernelGGL((k_update_jacobi<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
                          (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first,
-                         prr, pcs, prz);
+                         prr, pcs, prz, xf);
     else
       hipLaunchKernelGGL((k_update_jacobi<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
                          (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first,
-                         prr, pcs, prz);
+                         prr, pcs, prz, xf);
+  }
+  static void xfinal(int n, void* x, const void* p, const double* scal, double* pcs, hipStream_t s) {
+    const int g = grid_units(n, RG);
+    if (!g) return;
+    hipLaunchKernelGGL((k_xfinal<T, W>), dim3(g * NS), dim3(kBlock), 0, s, n, (T*)x, (const T*)p, scal,
+                       pcs);
   }
   static void coarse(int nc, int ncp, const double* A, const void* b, void* x, hipStream_t s) {
 #ifndef CFC_COARSE_NO_MFMA
@@ -1443,6 +1504,7 @@ struct Launch {
     t.coarse = &coarse;
     t.jacobi = &jacobi;
     t.update_jacobi = &update_jacobi;
+    t.xfinal = &xfinal;
     t.dot = &dot;
     t.residual64 = &residual64;
     t.xupdate64 = &xupdate64;

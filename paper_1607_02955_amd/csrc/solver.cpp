@@ -347,11 +347,13 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       prof_begin(K_RESTRICT0);
       k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, bfz ? w.z.p : nullptr,
                       w.scal.as<double>(), first_x, w.part_ptr(P_RR), w.part_ptr(P_CS),
-                      w.part_ptr(P_RZ), bfz ? 1 : 0, s);
-      const double ub = d0.n * nw * (first_x ? 5 : 6) + 2.0 * es * d0.n + (bfz ? 2.0 * d0.n * w.W : 0.0);
+                      w.part_ptr(P_RZ), bfz ? 1 : 0, xfu ? 1 : 0, s);
+      const double ub = d0.n * nw * (xfu ? (first_x ? 4 : 3) : (first_x ? 5 : 6)) + 2.0 * es * d0.n +
+                        (bfz ? 2.0 * d0.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
-      g_rr = g_cs = grid_for(d0.n, k.rg);
+      g_rr = grid_for(d0.n, k.rg);
+      g_cs = xfu ? 0 : g_rr;  // with xfu the sums of x come with the last update
     } else {
       // r . S r (and the bfloat16 copy of z = S r when the product gathers it)
       k.jacobi(w.la[0], r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), bfz ? 1 : 0, s);
@@ -541,11 +543,12 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
   // depth one: z = S r_in is formed inside the product kernel
   // (or gathered from its bfloat16 copy in ws.z)
   const bool jac = nuse == 1 && w.nlev > 1;
-  k.spmm_pq(w.la[0], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, w.scal.as<double>(), first,
-            w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
-  const double sb = bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
-                        : d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) +
-                              (jac ? es * d0.n : 0.0);
+  k.spmm_pq(w.la[0], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, xfu ? w.x.p : nullptr,
+            w.scal.as<double>(), first, w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
+  const double sb = (bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
+                         : d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) +
+                               (jac ? es * d0.n : 0.0)) +
+                    (xfu && !first ? 2.0 * d0.n * nw : 0.0);
   prof_end(K_SPMM, sb);
   bytes += sb;
   finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
@@ -575,6 +578,21 @@ void Solver::capture_pair() {
 // between ws.rb and ws.ra; with use_graph the later iterations replay a
 // captured pair of iterations.
 int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every) {
+  const int it = pcg_iterations(rr0, inner_tol, max_inner, check_every);
+  if (xfu) {
+    // the product kernels applied every x update but the last one
+    Workspace& w = *ws;
+    const DevLevel& d0 = g->D->lv[0];
+    const int gcs = grid_for(d0.n, w.kt->rg);
+    w.kt->xfinal(d0.n, w.x.p, w.p.p, w.scal.as<double>(), w.part_ptr(P_CS), stream);
+    finalize(w.W, F_CS, gcs, w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
+    bytes += 3.0 * d0.n * w.W * (w.fp64 ? 8 : 4);
+  }
+  return it;
+}
+
+int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int max_inner,
+                           int check_every) {
   Workspace& w = *ws;
   const int W = w.W;
   vcycle(false, false, w.ra.p, nullptr);
@@ -702,6 +720,10 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   const bool jac1 = nuse == 1 && ws->nlev > 1;
   const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && ws->nlev > 2;
   bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
+  // Depth one: the product kernel carries the x updates (CFC_FUSE_X=0 keeps
+  // them in the update kernel).
+  const char* fx = std::getenv("CFC_FUSE_X");
+  xfu = jac1 && !(fx && fx[0] == '0');
   CFC_HIP(hipEventCreate(&ev0));
   CFC_HIP(hipEventCreate(&ev1));
   CFC_HIP(hipEventRecord(ev0, stream));

@@ -46,7 +46,8 @@ struct Solver {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int g_rz = 0, g_rr = 0, g_cs = 0;
   int nuse = 1;  // V-cycle depth
-  bool bfz = false;  // depth one: z = S r stored as bfloat16 in ws->z
+  bool bfz = false;  // Jacobi paths: z = M^-1 r stored as bfloat16 in ws->z
+  bool xfu = false;  // depth one: x updates applied by the product kernel
   // statistics
   int64_t columns = 0, converged = 0, inner_iters = 0, refine_steps = 0, blocks = 0;
   double max_rel = 0, bytes = 0;
@@ -78,6 +79,7 @@ struct Solver {
   void vcycle(bool update, bool first_x, const void* r_in, void* r_out);
   void vcycle_elim(bool update, bool first_x, const void* r_in, void* r_out);
   int pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
+  int pcg_iterations(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
   void solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& p, int32_t* status,
                    double* final_rel);
   void read_scal(int which, double* out);
