@@ -73,9 +73,11 @@ struct KernTable {
   // Level-0 update and pre-smooth/residual/restrict:
   //   update: r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, partials |r_out|^2, sum x
   //   restrict (if nagg > 0): bc[I] = sum_{u in I} (b - L S b)_u with b = r_out, S = omega D^-1
+  //   xf = 1: x is left to spmm_pq (x = 0 on the first iteration, p not
+  //   read, no sum-x partials)
   void (*update_restrict)(const LevelArgs&, const void* r_in, const void* q, const void* p,
                           void* x, void* r_out, void* bc, const double* scal, int first,
-                          int do_update, double* part_rr, double* part_cs, hipStream_t);
+                          int do_update, double* part_rr, double* part_cs, int xf, hipStream_t);
   // Coarse-level pre-smooth/residual/restrict from b (no update).
   void (*restrict_)(const LevelArgs&, const void* b, void* bc, hipStream_t);
   // Prolong + post-smooth: xt = S b + mu xc[agg], x = xt + S (b - L xt); partial b.x if part

@@ -395,12 +395,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
 // bc[I] = sum_{u in I} (b - L S b)_u with b = r_out, which, the rows of an
 // aggregate being contiguous, is (1 - omega) sum_{u in I} b_u plus the sum,
 // over every edge leaving a row of I, of w_e * omega / D_vv * b_v.
-// Units are aggregates when RESTRICT, else rows.
+// Units are aggregates when RESTRICT, else rows.  xf: x is updated by the
+// next product kernel instead (x = 0 on the first iteration, p not read, no
+// sum-x partials).
 template <typename T, int W, bool UPDATE, bool RESTRICT, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_update_restrict(
     LevelArgs L, const T* __restrict__ r_in, const T* __restrict__ q, const T* __restrict__ p,
     T* __restrict__ x, T* __restrict__ r_out, T* __restrict__ bc, const double* __restrict__ scal,
-    int first, double* __restrict__ part_rr, double* __restrict__ part_cs) {
+    int first, double* __restrict__ part_rr, double* __restrict__ part_cs, int xf) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   using D = Deco<W, SPLIT>;
   __shared__ double lds[UPDATE ? RG * WS : 1];
@@ -435,17 +437,23 @@ __global__ __launch_bounds__(kBlock) void k_update_restrict(
         const size_t o = (size_t)u * W + c0;
         Vec<T, V> rn = ld<T, V>(r_in + o);
         if (UPDATE) {
-          const Vec<T, V> qu = ld<T, V>(q + o), pu = ld_nt<T, V>(p + o);
-          Vec<T, V> xu;
-          if (!first) xu = ld_nt<T, V>(x + o);
+          const Vec<T, V> qu = ld<T, V>(q + o);
+          Vec<T, V> xu, pu;
+          if (!xf) {
+            pu = ld_nt<T, V>(p + o);
+            if (!first) xu = ld_nt<T, V>(x + o);
+          }
 #pragma unroll
           for (int i = 0; i < V; ++i) {
             rn.v[i] -= alpha[i] * qu.v[i];
-            xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
+            if (xf)
+              xu.v[i] = 0;
+            else
+              xu.v[i] = first ? alpha[i] * pu.v[i] : xu.v[i] + alpha[i] * pu.v[i];
             rr[i] += double(rn.v[i]) * double(rn.v[i]);
             cs[i] += double(xu.v[i]);
           }
-          st_nt<T, V>(x + o, xu);
+          if (!xf || first) st_nt<T, V>(x + o, xu);
           st<T, V>(r_out + o, rn);
         }
 #pragma unroll
@@ -478,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_update_restrict(
   }
   if (UPDATE) {
     block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
-    block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
+    if (!xf) block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
   }
 }
 
@@ -1317,11 +1325,11 @@ struct Launch {
   }
   static void update_restrict(const LevelArgs& L, const void* r_in, const void* q, const void* p,
                               void* x, void* r_out, void* bc, const double* scal, int first,
-                              int do_update, double* prr, double* pcs, hipStream_t s) {
+                              int do_update, double* prr, double* pcs, int xf, hipStream_t s) {
     const bool R = L.nagg > 0;
     if (R && do_update) heavy<HK_RESTRICT_UPD>(L, r_in, q, nullptr, scal, s);
     else if (R) heavy<HK_RESTRICT>(L, r_in, nullptr, nullptr, scal, s);
-#define ARGS L, (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal, first, prr, pcs
+#define ARGS L, (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, (T*)bc, scal, first, prr, pcs, xf
     if (do_update && R)
       CFC_LAUNCH(k_update_restrict, L.nagg, T, W, true, true);
     else if (do_update)
@@ -1333,7 +1341,7 @@ struct Launch {
   static void restrict_(const LevelArgs& L, const void* b, void* bc, hipStream_t s) {
     heavy<HK_RESTRICT>(L, b, nullptr, nullptr, nullptr, s);
 #define ARGS L, (const T*)b, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)bc, \
-             (const double*)nullptr, 0, (double*)nullptr, (double*)nullptr
+             (const double*)nullptr, 0, (double*)nullptr, (double*)nullptr, 0
     CFC_LAUNCH(k_update_restrict, L.nagg, T, W, false, true);
 #undef ARGS
   }

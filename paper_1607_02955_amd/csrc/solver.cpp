@@ -348,8 +348,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, bfz ? w.z.p : nullptr,
                       w.scal.as<double>(), first_x, w.part_ptr(P_RR), w.part_ptr(P_CS),
                       w.part_ptr(P_RZ), bfz ? 1 : 0, xfu ? 1 : 0, s);
-      const double ub = d0.n * nw * (xfu ? (first_x ? 4 : 3) : (first_x ? 5 : 6)) + 2.0 * es * d0.n +
-                        (bfz ? 2.0 * d0.n * w.W : 0.0);
+      const double ub = d0.n * nw * upd_blocks(first_x) + 2.0 * es * d0.n + (bfz ? 2.0 * d0.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
       g_rr = grid_for(d0.n, k.rg);
@@ -371,9 +370,10 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       LevelArgs a = w.la[0];
       a.nagg = 0;
       k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
-                        1, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
-      g_rr = g_cs = k.rows_grid(a, d0.n);
-      bytes += d0.n * nw * (first_x ? 5 : 6);
+                        1, w.part_ptr(P_RR), w.part_ptr(P_CS), xfu ? 1 : 0, s);
+      g_rr = k.rows_grid(a, d0.n);
+      g_cs = xfu ? 0 : g_rr;
+      bytes += d0.n * nw * upd_blocks(first_x);
     }
     k.coarse(g->D->nc, (g->D->nc + 15) / 16 * 16, g->D->cpinv.as<double>(), rsrc, w.z.p, s);
     k.dot(d0.n, rsrc, w.z.p, w.part_ptr(P_RZ), s);
@@ -383,12 +383,13 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   }
   if (update) prof_begin(K_RESTRICT0);
   k.update_restrict(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.b[1].p, w.scal.as<double>(),
-                    first_x, update ? 1 : 0, w.part_ptr(P_RR), w.part_ptr(P_CS), s);
-  const double rb = d0.n * nw * (update ? (first_x ? 5 : 6) : 1) + d0.nagg * nw +
+                    first_x, update ? 1 : 0, w.part_ptr(P_RR), w.part_ptr(P_CS), xfu ? 1 : 0, s);
+  const double rb = d0.n * nw * (update ? upd_blocks(first_x) : 1) + d0.nagg * nw +
                     mat_bytes(d0, !d0.unit, es) + 4.0 * (d0.nagg + 1);
   if (update) {
     prof_end(K_RESTRICT0, rb);
-    g_rr = g_cs = k.rows_grid(w.la[0], d0.nagg);
+    g_rr = k.rows_grid(w.la[0], d0.nagg);
+    g_cs = xfu ? 0 : g_rr;
   }
   bytes += rb;
   for (int l = 1; l + 1 < L; ++l) {
@@ -438,11 +439,12 @@ void Solver::vcycle_elim(bool update, bool first_x, const void* r_in, void* r_ou
     LevelArgs a = w.la[0];
     a.nagg = 0;
     k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x, 1,
-                      w.part_ptr(P_RR), w.part_ptr(P_CS), s);
-    const double ub = n * nw * (first_x ? 5 : 6);
+                      w.part_ptr(P_RR), w.part_ptr(P_CS), xfu ? 1 : 0, s);
+    const double ub = n * nw * upd_blocks(first_x);
     prof_end(K_RESTRICT0, ub);
     bytes += ub;
-    g_rr = g_cs = k.rows_grid(a, n);
+    g_rr = k.rows_grid(a, n);
+    g_cs = xfu ? 0 : g_rr;
   }
   const double fb = 2.0 * nc * nw + (double)(n - nc) * nw + 8.0 * fw.nnz + 4.0 * nc;
   const double bb = (double)(n - nc) * nw * 2 + 2.0 * (n - nc) * nw + 16.0 * (n - nc);
@@ -720,10 +722,10 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   const bool jac1 = nuse == 1 && ws->nlev > 1;
   const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && ws->nlev > 2;
   bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
-  // Depth one: the product kernel carries the x updates (CFC_FUSE_X=0 keeps
-  // them in the update kernel).
+  // The product kernel carries the x updates (CFC_FUSE_X=0 keeps them in
+  // the update kernel).
   const char* fx = std::getenv("CFC_FUSE_X");
-  xfu = jac1 && !(fx && fx[0] == '0');
+  xfu = !(fx && fx[0] == '0');
   CFC_HIP(hipEventCreate(&ev0));
   CFC_HIP(hipEventCreate(&ev1));
   CFC_HIP(hipEventRecord(ev0, stream));

@@ -47,7 +47,10 @@ struct Solver {
   int g_rz = 0, g_rr = 0, g_cs = 0;
   int nuse = 1;  // V-cycle depth
   bool bfz = false;  // Jacobi paths: z = M^-1 r stored as bfloat16 in ws->z
-  bool xfu = false;  // depth one: x updates applied by the product kernel
+  bool xfu = false;  // x updates applied by the product kernel
+  // FP32/FP64 blocks streamed by the level-0 CG update (r_in, q, x, p read;
+  // x, r_out written; with xfu only r_in, q, r_out, and x = 0 the first time)
+  double upd_blocks(bool first) const { return xfu ? (first ? 4 : 3) : (first ? 5 : 6); }
   // statistics
   int64_t columns = 0, converged = 0, inner_iters = 0, refine_steps = 0, blocks = 0;
   double max_rel = 0, bytes = 0;
