@@ -100,9 +100,9 @@ struct KernTable {
   void (*coarse)(int nc, int nc_pad, const double* pinv, const void* b, void* x, hipStream_t);
   // Partial dots b.x over n rows (for the single-level case).
   void (*dot)(int n, const void* a, const void* b, double* part, hipStream_t);
-  // FP64 residual r = b - L x (x64 may be null = 0); r_out of element type T;
-  // partial |r|^2.
-  void (*residual64)(const LevelArgs& l64, const double* x64, RhsArgs rhs, void* r_out,
+  // FP64 residual r = b - L x (x may be null = 0; FP64, or FP32 when
+  // x_fp32); r_out of element type T; partial |r|^2.
+  void (*residual64)(const LevelArgs& l64, const void* x, int x_fp32, RhsArgs rhs, void* r_out,
                      double* part_rr, hipStream_t);
   // x64 = (first ? 0 : x64) + d - cs/n  (d of element type T; cs from scal)
   void (*xupdate64)(int n, double* x64, const void* d, const double* scal, int first, hipStream_t);

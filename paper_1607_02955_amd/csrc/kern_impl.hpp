@@ -243,7 +243,8 @@ __device__ __forceinline__ void add_heavy(const LevelArgs& L, int u, T* nb, int 
 // groups split the segment's edges and row group 0 stores the sum
 // hpart[seg] = sum_e w_e f(col_e) with f chosen by KIND.
 enum HeavyKind {
-  HK_SPMM = 0, HK_RESTRICT = 1, HK_RESTRICT_UPD = 2, HK_PROLONG = 3, HK_RES64 = 4, HK_BF16 = 5
+  HK_SPMM = 0, HK_RESTRICT = 1, HK_RESTRICT_UPD = 2, HK_PROLONG = 3, HK_RES64 = 4, HK_BF16 = 5,
+  HK_RES32 = 6  // T = double, the gathered block is FP32
 };
 
 template <typename T, int W, int KIND>
@@ -268,6 +269,13 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
     gather_acc<T, W>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
       if constexpr (KIND == HK_BF16)
         return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(a) + (size_t)v * W + c0);
+      if constexpr (KIND == HK_RES32) {
+        const Vec<float, V> f = ld<float, V>(reinterpret_cast<const float*>(a) + (size_t)v * W + c0);
+        Vec<T, V> r;
+#pragma unroll
+        for (int i = 0; i < V; ++i) r.v[i] = T(f.v[i]);
+        return r;
+      }
       Vec<T, V> r = ld<T, V>(a + (size_t)v * W + c0);
       if constexpr (KIND == HK_RESTRICT || KIND == HK_RESTRICT_UPD) {
         if constexpr (KIND == HK_RESTRICT_UPD) {
@@ -770,8 +778,23 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const T* __restrict__ a, 
 
 // ---------------------------------------------------------------------------
 // FP64 residual r = b - L x (Eq. 1), stored as TO; partial |r|^2 (FP64).
-template <typename TO, int W, int SPLIT>
-__global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double* __restrict__ x,
+// x is FP64, or (TX = float) an FP32 block whose values the FP64 arithmetic
+// takes exactly.
+template <typename TX, int V>
+__device__ __forceinline__ Vec<double, V> ld_f64(const TX* p) {
+  if constexpr (sizeof(TX) == 8) {
+    return ld<double, V>(p);
+  } else {
+    const Vec<TX, V> f = ld<TX, V>(p);
+    Vec<double, V> r;
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = double(f.v[i]);
+    return r;
+  }
+}
+
+template <typename TO, int W, typename TX, int SPLIT>
+__global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const TX* __restrict__ x,
                                                        RhsArgs rhs, TO* __restrict__ r_out,
                                                        double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
@@ -800,14 +823,14 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const double
     for (int i = 0; i < V; ++i) nb[i] = 0;
     if (x && u < L.n)
       gather_acc<double, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT,
-                            [&](int v) { return ld<double, V>(x + (size_t)v * W + c0); });
+                            [&](int v) { return ld_f64<TX, V>(x + (size_t)v * W + c0); });
     if constexpr (SPLIT > 1) wg_combine<double, W, SPLIT>(nb, ldc);
     if (u < L.n && D::leader(rg)) {
       if (x) add_heavy<double, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
       double a[V];
       if (x) {
-        const Vec<double, V> xu = ld<double, V>(x + o);
+        const Vec<double, V> xu = ld_f64<TX, V>(x + o);
         const double du = deg[u];
 #pragma unroll
         for (int i = 0; i < V; ++i) a[i] = du * xu.v[i] - nb[i];
@@ -1407,15 +1430,24 @@ struct Launch {
     hipLaunchKernelGGL((k_dot<T, W>), dim3(g * NS), dim3(kBlock), 0, s, n, (const T*)a, (const T*)b,
                        part);
   }
-  static void residual64(const LevelArgs& L, const double* x64, RhsArgs rhs, void* r_out,
+  static void residual64(const LevelArgs& L, const void* x, int x_fp32, RhsArgs rhs, void* r_out,
                          double* part, hipStream_t s) {
-    if (x64 && L.nseg)
-      hipLaunchKernelGGL((k_heavy<double, W, HK_RES64>), dim3(std::min(L.nseg, 4 * kMaxGrid) * NS),
-                         dim3(kBlock), 0, s, L, x64, (const double*)nullptr, (const double*)nullptr,
-                         (const double*)nullptr);
-#define ARGS L, x64, rhs, (T*)r_out, part
-    CFC_LAUNCH(k_residual64, L.n, T, W);
+    const dim3 gh(std::min(L.nseg, 4 * kMaxGrid) * NS);
+    if (x && L.nseg && x_fp32)
+      hipLaunchKernelGGL((k_heavy<double, W, HK_RES32>), gh, dim3(kBlock), 0, s, L, (const double*)x,
+                         (const double*)nullptr, (const double*)nullptr, (const double*)nullptr);
+    else if (x && L.nseg)
+      hipLaunchKernelGGL((k_heavy<double, W, HK_RES64>), gh, dim3(kBlock), 0, s, L, (const double*)x,
+                         (const double*)nullptr, (const double*)nullptr, (const double*)nullptr);
+    if (x_fp32) {
+#define ARGS L, (const float*)x, rhs, (T*)r_out, part
+      CFC_LAUNCH(k_residual64, L.n, T, W, float);
 #undef ARGS
+    } else {
+#define ARGS L, (const double*)x, rhs, (T*)r_out, part
+      CFC_LAUNCH(k_residual64, L.n, T, W, double);
+#undef ARGS
+    }
   }
   static void xupdate64(int n, double* x64, const void* d, const double* scal, int first,
                         hipStream_t s) {

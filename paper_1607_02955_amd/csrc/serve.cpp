@@ -218,7 +218,7 @@ void GraphWorker::run() {
       rhs.kind = 1;
       rhs.ps = ps;
       rhs.pt = pt;
-      w.kt->residual64(w.la64, w.x64.as<double>(), rhs, w.ra.p, w.part_ptr(P_PQ), stream);
+      w.kt->residual64(w.la64, w.x64.p, 0, rhs, w.ra.p, w.part_ptr(P_PQ), stream);
       finalize(W, F_R64, w.kt->rows_grid(w.la64, w.la64.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
                w.scal.as<double>(), stream, w.mirror_dev);
       sol->read_scal(S_R64, r64.data());

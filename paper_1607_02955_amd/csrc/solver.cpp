@@ -651,8 +651,14 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   double cur_max = 1.0;
   int step = 0;
   for (;; ++step) {
-    k.residual64(w.la64, have_x ? w.x64.as<double>() : nullptr, rhs, w.ra.p, w.part_ptr(P_PQ), s);
-    bytes += d0.n * (double)W * ((have_x ? 8.0 : 0.0) + (rhs.kind == 0 ? 8.0 : 0.0) + es) +
+    // After the first refinement step x64 = d - mean(d) with d the FP32
+    // inner solution still in ws.x, and L 1 = 0, so b - L x64 is b - L d up
+    // to FP64 rounding: the residual gathers the FP32 d (half the bytes),
+    // in FP64 arithmetic.  Later steps gather x64.
+    const bool x32 = have_x && step == 1 && !w.fp64;
+    k.residual64(w.la64, have_x ? (x32 ? w.x.p : w.x64.p) : nullptr, x32 ? 1 : 0, rhs, w.ra.p,
+                 w.part_ptr(P_PQ), s);
+    bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) + (rhs.kind == 0 ? 8.0 : 0.0) + es) +
              (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
     finalize(W, F_R64, gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s,
              w.mirror_dev);
