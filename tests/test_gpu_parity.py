@@ -354,14 +354,20 @@ def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
     rng = np.random.default_rng(9)
     s = rng.integers(0, eg.n, 2 * W + 3)
     t = rng.integers(0, eg.n, 2 * W + 3)
-    its = {}
-    for bz in ("0", "1"):
+    its, res = {}, {}
+    # (bfloat16 z, x updates in the product kernel): both off, z only, both on
+    for bz, fx in (("0", "0"), ("1", "0"), ("1", "1")):
         monkeypatch.setenv("CFC_BF16_Z", bz)
+        monkeypatch.setenv("CFC_FUSE_X", fx)
         r, st = g.resistance(s, t, block=W, tol=1e-8, levels=depth, stats=True, max_inner=3000)
-        say("bf16 z", case, bz, st["inner_iters"], st["refine_steps"])
+        say("bf16 z", case, bz, "fused x", fx, st["inner_iters"], st["refine_steps"])
         np.testing.assert_allclose(r, Rm[s, t], rtol=1e-7, atol=1e-12)
-        its[bz] = st["inner_iters"]
-    assert its["1"] <= 1.1 * its["0"] + 3
+        its[bz + fx], res[bz + fx] = st["inner_iters"], r
+    assert its["10"] <= 1.1 * its["00"] + 3
+    # carrying x in the product kernel is the same arithmetic (only the
+    # order of the column sums of x may differ)
+    assert its["11"] == its["10"]
+    np.testing.assert_allclose(res["11"], res["10"], rtol=1e-12, atol=1e-15)
 
 
 def test_elimination_to_two_nodes_is_exact(ctx):
