@@ -16,7 +16,8 @@ to 1e-10), rmat20_sampling (Sampling, 1000 pivots x 64 nodes, R-MAT scale 20),
 road2048_jl256 (projection k = 256 on a perturbed 2048^2 road grid),
 ba100k_shared1000 (shared-pivot Sampling), ba100k_cfb4096 (sampled
 current-flow betweenness), ba100k_spanning_jl512 (projection spanning-edge
-centrality of every edge), serve_mix (the serving loop) and setup_times
+centrality of every edge), ba100k_dense512 (cfc_solve of 512 dense
+right-hand sides in HBM), serve_mix (the serving loop) and setup_times
 (hierarchy setup, host build vs device build).
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
@@ -95,6 +96,11 @@ def make_workload(name):
         # sampled current-flow betweenness of every node from 4096 random pairs
         g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
         return g, dict(kind="cfb", k=4096, block=512, tol=1e-6, queries=0)
+    if name == "ba100k_dense512":
+        # cfc_solve of 512 dense mean-zero Gaussian right-hand sides held in
+        # HBM (column-major, graph node order)
+        g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
+        return g, dict(kind="dense", k=512, block=512, tol=1e-6, queries=0)
     if name == "ba100k_spanning_jl512":
         # projection spanning-edge centrality of all 399,990 edges, k = 512
         g = synth.cached("ba100000", synth.barabasi_albert, 100000, 4, seed=1)
@@ -224,8 +230,9 @@ def cpu_baseline(eg, spec, budget_s=20.0):
             return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",
                     "sample": f"{done} random source/sink pairs: oracle Jacobi-PCG (FP64) to rel. "
                               f"residual {spec['tol']:g} plus node throughput, {dt:.1f} s"}
-        if spec["kind"] in ("jl", "spanning_jl", "jl+sampling"):
-            Y = E.projection_rhs(eg, spec["k"], seed=1)
+        if spec["kind"] in ("jl", "spanning_jl", "jl+sampling", "dense"):
+            Y = spec["B"].T if spec["kind"] == "dense" else E.projection_rhs(eg, spec["k"], seed=1)
+            what = "dense Gaussian" if spec["kind"] == "dense" else "projection"
             cols = 1
             t0 = time.perf_counter()
             done = 0
@@ -236,7 +243,7 @@ def cpu_baseline(eg, spec, budget_s=20.0):
                 cols = min(cols * 2, 16)
             dt = time.perf_counter() - t0
             return {"value": done / dt, "unit": "solved RHS/s", "cores": 1, "kind": "oracle",
-                    "sample": f"first {done} of the {spec['k']} projection right-hand sides, "
+                    "sample": f"first {done} of the {spec['k']} {what} right-hand sides, "
                               f"oracle Jacobi-PCG (FP64) to rel. residual {spec['tol']:g}, {dt:.1f} s"}
         n = eg.n
         rng = np.random.default_rng(1)
@@ -366,6 +373,12 @@ def main():
         spec["block"] = args.block
     kw = dict(tol=spec["tol"], block=spec["block"], precision=prec, levels=args.levels,
               use_graph=use_graph, check_every=args.check_every, inner_tol=args.inner_tol)
+    if spec["kind"] == "dense":
+        rng = np.random.default_rng(1)
+        B = rng.standard_normal((spec["k"], eg.n))
+        B -= B.mean(axis=1, keepdims=True)
+        spec["B"] = B
+        Bd = torch.tensor(B, device="cuda")  # resident before the timed region
 
     def step(seed, **over):
         kw2 = dict(kw, **over)
@@ -396,6 +409,9 @@ def main():
             return st, st["columns"]
         if spec["kind"] == "spanning_jl":
             _, st = g.spanning_edge_jl(eg.u, eg.v, spec["k"], seed=seed, stats=True, **kw2)
+            return st, spec["k"]
+        if spec["kind"] == "dense":
+            _, st, _ = g.solve(Bd, stats=True, **kw2)
             return st, spec["k"]
         _, _, st = g.farness_exact(nodes, stats=True, **kw2)
         return st, st["columns"]
