@@ -324,6 +324,8 @@ def main():
     ap.add_argument("--burst", type=int, default=64, help="serve_mix: queries in the saturation burst")
     ap.add_argument("--no-full-depth", action="store_true",
                     help="skip the comparison run with the full multigrid depth")
+    ap.add_argument("--host-buffers", action="store_true",
+                    help="ba100k_dense512: right-hand sides and solutions in host memory (PCIe-inclusive)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -378,7 +380,9 @@ def main():
         B = rng.standard_normal((spec["k"], eg.n))
         B -= B.mean(axis=1, keepdims=True)
         spec["B"] = B
-        Bd = torch.tensor(B, device="cuda")  # resident before the timed region
+        # resident before the timed region, or (--host-buffers) host memory,
+        # for the PCIe-inclusive rate
+        Bd = B if args.host_buffers else torch.tensor(B, device="cuda")
 
     def step(seed, **over):
         kw2 = dict(kw, **over)
@@ -473,6 +477,8 @@ def main():
                   "whole_path_hbm_frac": round(agg["bytes"] / (dt * 1e9) / HBM_PEAK_GBS, 4),
                   "setup_s": round(setup_s, 3)},
     }
+    if spec["kind"] == "dense":
+        out["config"]["rhs_memory"] = "host (pageable, PCIe-inclusive)" if args.host_buffers else "hbm"
     if not args.no_full_depth and info["levels"] > 1 and agg["depth"] != info["levels"]:
         progress("full-depth comparison")
         # the same workload through the full multigrid depth, for comparison
