@@ -39,8 +39,7 @@ void upload(Ctx* c, DBuf& d, const std::vector<T>& h, hipStream_t s) {
 // cut into segments of heavy_deg edges, FP32 and FP64 weights.
 static void upload_csr(Ctx* c, DevLevel& d, int64_t n, const std::vector<int32_t>& rowptr,
                        const std::vector<int32_t>& col, const std::vector<double>& w, bool unit,
-                       int heavy_deg, hipStream_t s) {
-  const int seg_len = heavy_deg;
+                       int heavy_deg, int seg_len, hipStream_t s) {
   std::vector<int32_t> lptr(n + 1, 0), lcol, hid(n, -1), hptr(1, 0), hcol, hseg(1, 0), seg_e(1, 0),
       seg_row;
   std::vector<double> lw, hw;
@@ -123,6 +122,11 @@ void upload_hierarchy(Graph& g) {
     const char* e = std::getenv("CFC_HEAVY_DEG");
     return e ? std::max(16, std::atoi(e)) : 256;
   }();
+  // edges per heavy-row segment (one pre-pass workgroup per segment and slice)
+  static const int seg_len = [] {
+    const char* e = std::getenv("CFC_SEG_LEN");
+    return e ? std::max(16, std::atoi(e)) : heavy_deg;
+  }();
   for (int l = 0; l < L; ++l) {
     const HostLevel& h = H.lv[l];
     DevLevel& d = D->lv[l];
@@ -130,7 +134,7 @@ void upload_hierarchy(Graph& g) {
     d.nnz = (int)h.nnz();
     d.nagg = h.aggptr.empty() ? 0 : (int)h.aggptr.size() - 1;
     d.unit = (l == 0) && g.unit;
-    upload_csr(c, d, h.n, h.rowptr, h.col, h.w, d.unit, heavy_deg, s);
+    upload_csr(c, d, h.n, h.rowptr, h.col, h.w, d.unit, heavy_deg, seg_len, s);
     std::vector<float> deg32(h.n), sd32(h.n);
     std::vector<double> sd64(h.n);
     for (int64_t r = 0; r < h.n; ++r) {
@@ -154,7 +158,7 @@ void upload_hierarchy(Graph& g) {
       // elimination level: forward operator (kept rows x eliminated rows;
       // hubs with many eliminated neighbours go to short heavy segments)
       d.nC = (int)h.nC;
-      upload_csr(c, D->fwd, h.nC, h.fptr, h.fcol, h.fcoef, false, 64, s);
+      upload_csr(c, D->fwd, h.nC, h.fptr, h.fcol, h.fcoef, false, 64, 64, s);
       D->fwd.n = (int)h.nC;
       D->fwd.nnz = (int)h.fcol.size();
       upload(c, d.enb, h.enb, s);
