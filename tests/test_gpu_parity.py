@@ -281,6 +281,12 @@ def test_edge_cases(ctx):
         g2.resistance([0], [2])
     with pytest.raises(cfc.CfcError):
         g2.solve(np.array([1.0, 0.0]))  # does not sum to zero
+    # dense solves at the smallest sizes: one node (only b = 0), two nodes,
+    # no right-hand sides
+    np.testing.assert_array_equal(g1.solve(np.zeros((3, 1)), tol=1e-10), np.zeros((3, 1)))
+    np.testing.assert_allclose(g2.solve(np.array([[1.0, -1.0]]), tol=1e-10), [[0.125, -0.125]],
+                               rtol=1e-9)
+    assert g2.solve(np.zeros((0, 2))).shape == (0, 2)
     with pytest.raises(cfc.CfcError, match="STATE"):
         g2.farness_jl([0])
 
