@@ -52,6 +52,7 @@ struct RhsArgs {
   const double* dense = nullptr;
   const int* ps = nullptr;       // [W] row of +1 (or -1 = none)
   const int* pt = nullptr;       // [W] row of -1 (or -1 = none)
+  double* r64_out = nullptr;     // residual64: also store r in FP64 here (may be dense itself)
 };
 
 // Scalars kept per column on the device (double[kNScal][W]).

@@ -848,13 +848,16 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const TX* __
         for (int i = 0; i < V; ++i) bv[i] = (u == ps[i] ? 1.0 : 0.0) - (u == pt[i] ? 1.0 : 0.0);
       }
       Vec<TO, V> ro;
+      Vec<double, V> r64;
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const double r = bv[i] - a[i];
+        r64.v[i] = r;
         ro.v[i] = TO(r);
         acc[i] += r * r;
       }
       st_nt<TO, V>(r_out + o, ro);
+      if (rhs.r64_out) st_nt<double, V>(rhs.r64_out + o, r64);
     }
   }
   block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);

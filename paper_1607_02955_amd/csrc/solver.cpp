@@ -654,16 +654,35 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   const int gres = k.rows_grid(w.la64, d0.n);
   double cur_max = 1.0;
   int step = 0;
+  // FP32 inner solves aimed straight at tol (or FP64 ones) are expected to
+  // finish in one refinement step unless an earlier block of this solve
+  // needed more; otherwise the FP64 residual is kept for the next step
+  const bool direct = p.precision == CFC_PREC_FP64 || p.inner_tol < 1e-6;
+  bool r64_valid = false;  // ws.r64 = b - L x64 in FP64
   for (;; ++step) {
-    // After the first refinement step x64 = d - mean(d) with d the FP32
-    // inner solution still in ws.x, and L 1 = 0, so b - L x64 is b - L d up
-    // to FP64 rounding: the residual gathers the FP32 d (half the bytes),
-    // in FP64 arithmetic.  Later steps gather x64.
-    const bool x32 = have_x && step == 1 && !w.fp64;
-    k.residual64(w.la64, have_x ? (x32 ? w.x.p : w.x64.p) : nullptr, x32 ? 1 : 0, rhs, w.ra.p,
+    // x64 = x64_prev + d - mean(d) with d the FP32 inner solution still in
+    // ws.x, and L 1 = 0, so b - L x64 = r_prev - L d up to FP64 rounding,
+    // where r_prev is b after the first step and the kept FP64 residual
+    // after later ones.  That residual gathers the FP32 d (half the bytes of
+    // x64) and computes in FP64; without a kept residual (a step that was
+    // expected to be the last) it gathers x64.
+    const bool x32 = have_x && !w.fp64 && (step == 1 || r64_valid);
+    RhsArgs rr = rhs;
+    if (x32 && step >= 2) {
+      rr.kind = 0;
+      rr.dense = w.r64.as<double>();
+    }
+    const bool keep = !w.fp64 && have_x && (!direct || multi_step) && step < p.max_refine;
+    if (keep) {
+      if (!w.r64.p) w.r64.alloc(g->ctx, (size_t)d0.n * W * sizeof(double));
+      rr.r64_out = w.r64.as<double>();
+    }
+    k.residual64(w.la64, have_x ? (x32 ? w.x.p : w.x64.p) : nullptr, x32 ? 1 : 0, rr, w.ra.p,
                  w.part_ptr(P_PQ), s);
-    bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) + (rhs.kind == 0 ? 8.0 : 0.0) + es) +
+    bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) + (rr.kind == 0 ? 8.0 : 0.0) + es +
+                                 (keep ? 8.0 : 0.0)) +
              (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
+    r64_valid = keep;
     finalize(W, F_R64, gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s,
              w.mirror_dev);
     read_scal(S_R64, r64.data());
@@ -686,7 +705,6 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     // inner solve can be trusted to land near it (FP64 inner solves, or FP32
     // ones aimed straight at the target, inner_tol < 1e-6); 0.5 when FP32
     // rounding may leave the true residual above the recursive one.
-    const bool direct = p.precision == CFC_PREC_FP64 || p.inner_tol < 1e-6;
     const double aim = direct ? 0.9 : 0.5;
     double itol = p.precision == CFC_PREC_FP64 ? std::max(aim * p.tol / cur_max, 1e-15)
                                                 : std::max(p.inner_tol, aim * p.tol / cur_max);
@@ -698,6 +716,7 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     bytes += d0.n * (double)W * ((have_x ? 16.0 : 8.0) + es);
     have_x = true;
     refine_steps++;
+    if (step >= 1) multi_step = true;
   }
   if (!have_x) k.zero(w.x64.p, (size_t)d0.n * W * 8, s);
   for (int j = 0; j < ncols; ++j) {

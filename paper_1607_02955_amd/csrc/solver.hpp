@@ -25,6 +25,7 @@ struct Workspace {
   DBuf fpart;                 // its heavy-row segment partials
   DBuf x64;                   // FP64 solution block
   DBuf rhs;                   // FP64 dense right-hand sides (on demand)
+  DBuf r64;                   // FP64 residual kept between refinement steps (on demand)
   DBuf pairs;                 // int32 ps[W], pt[W], segment bounds
   DBuf part;                  // FP64 partial sums [P_COUNT][kMaxGrid][W]
   DBuf scal;                  // FP64 per-column scalars [S_N][W]
@@ -48,6 +49,7 @@ struct Solver {
   int nuse = 1;  // V-cycle depth
   bool bfz = false;  // Jacobi paths: z = M^-1 r stored as bfloat16 in ws->z
   bool xfu = false;  // x updates applied by the product kernel
+  bool multi_step = false;  // a block of this solve took more than one refinement step
   // FP32/FP64 blocks streamed by the level-0 CG update (r_in, q, x, p read;
   // x, r_out written; with xfu only r_in, q, r_out, and x = 0 the first time)
   double upd_blocks(bool first) const { return xfu ? (first ? 4 : 3) : (first ? 5 : 6); }
