@@ -30,18 +30,20 @@ const KernTable* kern_table(int W, bool fp64) {
 }
 
 int grid_for(int units, int rg) {
-  // workgroups per column slice: 1024 (8192 in all at eight slices) keep
-  // the level-0 kernels at full speed while the partial sums that the
-  // finalize step reads stay half the size of a 2048 cap (measured: +4% on
-  // the BA-100k projection, unchanged on road grids and R-MAT).
-  // CFC_GRID_CAP overrides it for measurements, at most kMaxGrid (the
-  // partial-sum buffers' row count).
-  static const int cap = [] {
+  // Workgroups per column slice.  Large levels take 1024 (8192 in all at
+  // eight slices, four rounds of the 2048 that are resident at once); levels
+  // of at most 8192 row tiles take 512, so that each workgroup walks at
+  // least a dozen tiles and the partial sums stay small (measured on the
+  // level-0 kernels: BA-100k projection +2.4% at 512, R-MAT-20 and
+  // road-2048 levels 5-6% slower there).  CFC_GRID_CAP fixes one cap for
+  // every level, at most kMaxGrid (the partial-sum buffers' row count).
+  static const int fixed = [] {
     const char* e = std::getenv("CFC_GRID_CAP");
-    return e ? std::max(8, std::min(kMaxGrid, std::atoi(e))) : kMaxGrid / 2;
+    return e ? std::max(8, std::min(kMaxGrid, std::atoi(e))) : 0;
   }();
   if (units <= 0) return 0;
   int tiles = (units + rg - 1) / rg;
+  const int cap = fixed ? fixed : (tiles <= 8192 ? kMaxGrid / 4 : kMaxGrid / 2);
   int g = std::min(tiles, cap);
   if (g >= 64) g &= ~7;
   return g;
