@@ -330,8 +330,9 @@ def main():
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the path would shard right-hand-side columns across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path would shard right-hand-side columns across GPUs, one all-reduce of the "
+              "per-node sums at the end)", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("CFC_PROFILE", "1")
     import numpy as np

@@ -1,4 +1,4 @@
-// Solve driver: device copy of the hierarchy, per-block workspaces, the
+// Solve loop: device copy of the hierarchy, per-block workspaces, the
 // preconditioned CG inner solver, FP64 iterative refinement, and the
 // estimator reductions.
 //

@@ -1,4 +1,4 @@
-// Solver driver declarations.
+// Solver declarations.
 #pragma once
 #include <vector>
 

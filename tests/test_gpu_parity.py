@@ -1,6 +1,6 @@
 """GPU parity of the HIP solve path against the CPU oracle (through the C ABI).
 
-Tolerances: the solve is judged on relative farness / resistance error
+Tolerances: the solve is checked on relative farness / resistance error
 (<= 1e-6 at the tolerances used below, tighter in FP64 mode); estimator
 outputs must match the oracle's for the same seed to <= 1e-4 relative.
 """
