@@ -349,13 +349,10 @@ void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p0, c
   if (!w.rhs.p) w.rhs.alloc(g.ctx, (size_t)n0 * W * sizeof(double));
   if (g.jl.N_dev.bytes != (size_t)n0 * 8) {
     g.jl.N_dev.alloc(g.ctx, (size_t)n0 * 8);
-    g.jl.T_dev.alloc(g.ctx, (size_t)n0 * 8);
     g.jl.S2_dev.alloc(g.ctx, 1024 * 8 + 8);
   }
   w.kt->zero(g.jl.N_dev.p, g.jl.N_dev.bytes, S.stream);
-  w.kt->zero(g.jl.T_dev.p, g.jl.T_dev.bytes, S.stream);
   LevelArgs l64 = w.la64;
-  const int grow = grid_for(n0, w.kt->rg);
   std::vector<int32_t> stat(W);
   for (int64_t i0 = 0; i0 < k; i0 += W) {
     const int nc = (int)std::min<int64_t>(W, k - i0);
@@ -365,11 +362,9 @@ void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p0, c
     r.kind = 0;
     r.dense = w.rhs.as<double>();
     S.solve_block(r, nc, p, stat.data(), nullptr);
-    // per-node |Z_v|^2, column sums s, then Z_v . s
-    w.kt->jl_rownorm(n0, w.x64.as<double>(), nc, g.jl.N_dev.as<double>(), w.part_ptr(P_CS), S.stream);
-    finalize(W, F_CS, grow, w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(), S.stream);
-    w.kt->jl_rowdot(n0, w.x64.as<double>(), nc, w.scal.as<double>(), g.jl.T_dev.as<double>(), S.stream);
-    S.bytes += 2.0 * n0 * W * 8 + 4.0 * n0 * 8;
+    // per-node |Z_v|^2 (the solutions are mean-zero, so sum_w Z_w = 0)
+    w.kt->jl_rownorm(n0, w.x64.as<double>(), nc, g.jl.N_dev.as<double>(), nullptr, S.stream);
+    S.bytes += (double)n0 * W * 8 + 2.0 * n0 * 8;
   }
   double* part = g.jl.S2_dev.as<double>() + 1;
   reduce_sum(n0, g.jl.N_dev.as<double>(), part, g.jl.S2_dev.as<double>(), S.stream);
@@ -395,22 +390,20 @@ void jl_farness(Graph& g, int64_t q, const int64_t* nodes, double* far, double* 
   }
   if (q == 0) return;
   Ctx* c = mem ? mem : g.ctx;
-  DBuf di, dn, dt;
+  DBuf di, dn;
   di.alloc(c, q * sizeof(int));
   dn.alloc(c, q * sizeof(double));
-  dt.alloc(c, q * sizeof(double));
   hipStream_t s = stream ? stream : g.ctx->stream;
   CFC_HIP(hipMemcpyAsync(di.p, idx.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
   gather((int)q, g.jl.N_dev.as<double>(), di.as<int>(), dn.as<double>(), s);
-  gather((int)q, g.jl.T_dev.as<double>(), di.as<int>(), dt.as<double>(), s);
-  std::vector<double> hn(q), ht(q);
+  std::vector<double> hn(q);
   CFC_HIP(hipMemcpyAsync(hn.data(), dn.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
-  CFC_HIP(hipMemcpyAsync(ht.data(), dt.p, q * sizeof(double), hipMemcpyDeviceToHost, s));
   CFC_HIP(hipStreamSynchronize(s));
   const double n = (double)g.n;
   for (int64_t i = 0; i < q; ++i) {
-    // sum_w |Z_v - Z_w|^2 = n |Z_v|^2 - 2 Z_v . sum_w Z_w + |Z|_F^2
-    const double f = n * hn[i] - 2.0 * ht[i] + g.jl.S2;
+    // sum_w |Z_v - Z_w|^2 = n |Z_v|^2 - 2 Z_v . sum_w Z_w + |Z|_F^2, and
+    // sum_w Z_w = 0 because every solve returns the mean-zero L^+ y_i
+    const double f = n * hn[i] + g.jl.S2;
     far[i] = f;
     if (clo) clo[i] = f > 0 ? (n - 1) / f : INFINITY;
   }

@@ -132,7 +132,6 @@ struct JLSketch {
   int64_t k = 0;
   uint64_t seed = 0;
   DBuf N_dev;   // per level-0 row ||Z_.v||^2
-  DBuf T_dev;   // per level-0 row Z_.v . sum_w Z_.w
   DBuf S2_dev;  // ||Z||_F^2 and reduction scratch
   double S2 = 0;
   bool valid = false;

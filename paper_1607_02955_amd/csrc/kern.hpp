@@ -110,10 +110,9 @@ struct KernTable {
   // Projection right-hand sides (Algorithm 1): Y[u, j] for systems i0 + j < k.
   void (*jl_rhs)(const LevelArgs& l64, const int* iperm, uint64_t seed, int64_t i0, int64_t k,
                  double* Y, hipStream_t);
-  // Per-row |x_u|^2 accumulated into N (double[n]) and partial column sums.
+  // Per-row |x_u|^2 accumulated into N (double[n]); partial column sums
+  // into part_cs when it is non-null.
   void (*jl_rownorm)(int n, const double* x64, int ncols, double* N, double* part_cs, hipStream_t);
-  // T[u] += x_u . s  (s = column sums, scal S_CS)
-  void (*jl_rowdot)(int n, const double* x64, int ncols, const double* scal, double* T, hipStream_t);
   void (*zero)(void* p, size_t bytes, hipStream_t);
   // Elimination level, forward step over the kept rows (lf = the forward
   // operator, lf.n = kept rows): t = r + F r.  jac = 0 writes t to out;

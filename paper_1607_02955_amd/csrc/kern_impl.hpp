@@ -974,32 +974,6 @@ __global__ __launch_bounds__(kBlock) void k_jl_rownorm(int n, const double* __re
   }
 }
 
-// T[u] += x_u . s with s the column sums held in scal[S_CS].
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_jl_rowdot(int n, const double* __restrict__ x, int ncols,
-                                                      const double* __restrict__ scal,
-                                                      double* __restrict__ Tv) {
-  constexpr int LPR = RowShape<W>::LPR, V = RowShape<W>::V, RG = RowShape<W>::RG;
-  const int rg = threadIdx.x / LPR, lane = threadIdx.x % LPR, c0 = lane * V;
-  double sc[V];
-#pragma unroll
-  for (int i = 0; i < V; ++i) sc[i] = (c0 + i < ncols) ? scal[S_CS * W + c0 + i] : 0.0;
-  int tb, te;
-  block_tiles((n + RG - 1) / RG, blockIdx.x, gridDim.x, tb, te);
-  for (int t = tb; t < te; ++t) {
-    const int u = t * RG + rg;
-    const bool ok = u < n;
-    double s = 0;
-    if (ok) {
-      const Vec<double, V> xu = ld<double, V>(x + (size_t)u * W + c0);
-#pragma unroll
-      for (int i = 0; i < V; ++i) s += xu.v[i] * sc[i];
-    }
-    for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
-    if (ok && lane == 0) Tv[u] += s;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Elimination level (LAMG's elimination stage): with the kept rows C first
 // and the eliminated rows F an independent set, L = [L_CC L_CF; L_FC D_F]
@@ -1471,16 +1445,11 @@ struct Launch {
     const int g = grid_units(n, RowShape<W>::RG);
     if (!g) return;
     hipLaunchKernelGGL((k_jl_rownorm<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, N);
+    if (!part) return;
     // column sums of the block, sliced like the other partial sums
     const int gc = grid_units(n, RG);
     hipLaunchKernelGGL((k_dot<double, W>), dim3(gc * NS), dim3(kBlock), 0, s, n, x64,
                        (const double*)nullptr, part);
-  }
-  static void jl_rowdot(int n, const double* x64, int ncols, const double* scal, double* Tv,
-                        hipStream_t s) {
-    const int g = grid_units(n, RowShape<W>::RG);
-    if (!g) return;
-    hipLaunchKernelGGL((k_jl_rowdot<W>), dim3(g), dim3(kBlock), 0, s, n, x64, ncols, scal, Tv);
   }
   static int elim_grid(int units) { return std::min(grid_units(units, RG), kMaxGrid / 2); }
   static void elim_fwd(const LevelArgs& L, const void* r, void* out, const void* sd1,
@@ -1553,7 +1522,6 @@ struct Launch {
     t.xupdate64 = &xupdate64;
     t.jl_rhs = &jl_rhs;
     t.jl_rownorm = &jl_rownorm;
-    t.jl_rowdot = &jl_rowdot;
     t.zero = &zero;
     t.throughput = &throughput;
     t.elim_fwd = &elim_fwd;
