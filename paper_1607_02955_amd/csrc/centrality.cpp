@@ -254,10 +254,12 @@ void spanning_edge_jl(Graph& g, int64_t ne, const int64_t* u, const int64_t* v, 
   std::vector<int32_t> stat(W);
   for (int64_t i0 = 0; i0 < k; i0 += W) {
     const int nc = (int)std::min<int64_t>(W, k - i0);
-    w.kt->jl_rhs(w.la64, g.D->iperm.as<int>(), seed, i0, k, w.rhs.as<double>(), S.stream);
+    const int rows = w.kt->jl_rhs(w.la64, g.D->iperm.as<int>(), seed, i0, k, w.rhs.as<double>(), w.ra.p,
+                                  w.part_ptr(P_PQ), S.stream);
     RhsArgs r;
     r.kind = 0;
     r.dense = w.rhs.as<double>();
+    r.r0_rows = rows;
     S.solve_block(r, nc, p, stat.data(), nullptr);
     require_converged(stat, nc);
     w.kt->edge_sq((int)ne, da.as<int>(), db.as<int>(), w.x64.as<double>(), nc, dout.as<double>(),

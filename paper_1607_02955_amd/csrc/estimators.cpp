@@ -356,11 +356,15 @@ void jl_sketch(Graph& g, int64_t k, uint64_t seed, const cfc_solve_params& p0, c
   std::vector<int32_t> stat(W);
   for (int64_t i0 = 0; i0 < k; i0 += W) {
     const int nc = (int)std::min<int64_t>(W, k - i0);
-    w.kt->jl_rhs(l64, g.D->iperm.as<int>(), seed, i0, k, w.rhs.as<double>(), S.stream);
-    S.bytes += (double)n0 * W * 8 + 4.0 * g.D->lv[0].nnz + 8.0 * n0;
+    // the right-hand sides, with the refinement's first residual (r = y in
+    // the inner precision) and its norms formed in the same pass
+    const int rows = w.kt->jl_rhs(l64, g.D->iperm.as<int>(), seed, i0, k, w.rhs.as<double>(), w.ra.p,
+                                  w.part_ptr(P_PQ), S.stream);
+    S.bytes += (double)n0 * W * (8 + w.kt->esize) + 4.0 * g.D->lv[0].nnz + 8.0 * n0;
     RhsArgs r;
     r.kind = 0;
     r.dense = w.rhs.as<double>();
+    r.r0_rows = rows;
     S.solve_block(r, nc, p, stat.data(), nullptr);
     // per-node |Z_v|^2 (the solutions are mean-zero, so sum_w Z_w = 0)
     w.kt->jl_rownorm(n0, w.x64.as<double>(), nc, g.jl.N_dev.as<double>(), nullptr, S.stream);

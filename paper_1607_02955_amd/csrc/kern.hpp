@@ -53,6 +53,8 @@ struct RhsArgs {
   const int* ps = nullptr;       // [W] row of +1 (or -1 = none)
   const int* pt = nullptr;       // [W] row of -1 (or -1 = none)
   double* r64_out = nullptr;     // residual64: also store r in FP64 here (may be dense itself)
+  int r0_rows = 0;               // > 0: the first residual (r = b, in the solver's r_a) and
+                                 // its partial sums of r^2 (this many rows) are already formed
 };
 
 // Scalars kept per column on the device (double[kNScal][W]).
@@ -108,8 +110,10 @@ struct KernTable {
   // x64 = (first ? 0 : x64) + d - cs/n  (d of element type T; cs from scal)
   void (*xupdate64)(int n, double* x64, const void* d, const double* scal, int first, hipStream_t);
   // Projection right-hand sides (Algorithm 1): Y[u, j] for systems i0 + j < k.
-  void (*jl_rhs)(const LevelArgs& l64, const int* iperm, uint64_t seed, int64_t i0, int64_t k,
-                 double* Y, hipStream_t);
+  // r (nullable): also Y in element type T and partial sums of Y^2 into
+  // part.  Returns the rows of partial sums (the grid per column slice).
+  int (*jl_rhs)(const LevelArgs& l64, const int* iperm, uint64_t seed, int64_t i0, int64_t k,
+                double* Y, void* r, double* part, hipStream_t);
   // Per-row |x_u|^2 accumulated into N (double[n]); partial column sums
   // into part_cs when it is non-null.
   void (*jl_rownorm)(int n, const double* x64, int ncols, double* N, double* part_cs, hipStream_t);

@@ -883,11 +883,18 @@ __global__ __launch_bounds__(kBlock) void k_xupdate64(int n, double* __restrict_
 // is system i = i0 + j, y_i[u] = sum over edges {u,v} of B(e,u) q_i(e) sqrt(w_e)
 // with B(e, lo) = +1, B(e, hi) = -1 and q_i(e) = +-1/sqrt(k) from the sign
 // word of (seed, i/64, lo, hi), bit i%64 (set = -1), keyed on graph ids.
-template <int W>
+// r (nullable): the same values in the inner precision TO, with partial sums
+// of y^2 (the refinement's first residual, r = y, and its norms).
+template <typename TO, int W>
 __global__ __launch_bounds__(kBlock) void k_jl_rhs(LevelArgs L, const int* __restrict__ iperm,
                                                    uint64_t seed, int64_t i0, int64_t k,
-                                                   double* __restrict__ Y) {
+                                                   double* __restrict__ Y, TO* __restrict__ r,
+                                                   double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  __shared__ double lds[RG * WS];
+  double acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = 0;
   int slice, rb, grb;
   slice_of_block<W>(slice, rb, grb);
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
@@ -941,7 +948,17 @@ __global__ __launch_bounds__(kBlock) void k_jl_rhs(LevelArgs L, const int* __res
 #pragma unroll
     for (int i = 0; i < V; ++i) yo.v[i] = (sys0 + i < k) ? a[i] * inv_sqrt_k : 0.0;
     st<double, V>(Y + (size_t)u * W + c0, yo);
+    if (r) {
+      Vec<TO, V> ro;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        ro.v[i] = TO(yo.v[i]);
+        acc[i] += yo.v[i] * yo.v[i];
+      }
+      st_nt<TO, V>(r + (size_t)u * W + c0, ro);
+    }
   }
+  if (r) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // Whole-row shape (no column slicing) for per-row reductions over all W columns.
@@ -1434,11 +1451,13 @@ struct Launch {
     hipLaunchKernelGGL((k_xupdate64<T, W>), dim3(g), dim3(kBlock), 0, s, n, x64, (const T*)d, scal,
                        first);
   }
-  static void jl_rhs(const LevelArgs& L, const int* iperm, uint64_t seed, int64_t i0, int64_t k,
-                     double* Y, hipStream_t s) {
+  static int jl_rhs(const LevelArgs& L, const int* iperm, uint64_t seed, int64_t i0, int64_t k,
+                    double* Y, void* r, double* part, hipStream_t s) {
     const int g = grid_units(L.n, RG);
-    if (!g) return;
-    hipLaunchKernelGGL((k_jl_rhs<W>), dim3(g * NS), dim3(kBlock), 0, s, L, iperm, seed, i0, k, Y);
+    if (!g) return 0;
+    hipLaunchKernelGGL((k_jl_rhs<T, W>), dim3(g * NS), dim3(kBlock), 0, s, L, iperm, seed, i0, k, Y,
+                       (T*)r, part);
+    return g;
   }
   static void jl_rownorm(int n, const double* x64, int ncols, double* N, double* part,
                          hipStream_t s) {

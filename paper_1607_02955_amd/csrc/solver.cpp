@@ -677,14 +677,18 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
       if (!w.r64.p) w.r64.alloc(g->ctx, (size_t)d0.n * W * sizeof(double));
       rr.r64_out = w.r64.as<double>();
     }
-    k.residual64(w.la64, have_x ? (x32 ? w.x.p : w.x64.p) : nullptr, x32 ? 1 : 0, rr, w.ra.p,
-                 w.part_ptr(P_PQ), s);
-    bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) + (rr.kind == 0 ? 8.0 : 0.0) + es +
-                                 (keep ? 8.0 : 0.0)) +
-             (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
+    // the first residual r = b may come with the right-hand sides
+    const bool pre = step == 0 && rhs.r0_rows > 0;
+    if (!pre) {
+      k.residual64(w.la64, have_x ? (x32 ? w.x.p : w.x64.p) : nullptr, x32 ? 1 : 0, rr, w.ra.p,
+                   w.part_ptr(P_PQ), s);
+      bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) + (rr.kind == 0 ? 8.0 : 0.0) +
+                                   es + (keep ? 8.0 : 0.0)) +
+               (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
+    }
     r64_valid = keep;
-    finalize(W, F_R64, gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), s,
-             w.mirror_dev);
+    finalize(W, F_R64, pre ? rhs.r0_rows : gres, w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
+             w.scal.as<double>(), s, w.mirror_dev);
     read_scal(S_R64, r64.data());
     if (step == 0) b2 = r64;
     bool all = true;
