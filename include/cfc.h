@@ -314,7 +314,7 @@ int cfc_farness_sampling_shared(cfc_graph* g, int64_t q, const int64_t* nodes,
                                 int64_t k, uint64_t seed, double* far, double* clo,
                                 const cfc_solve_params* p, cfc_solve_stats* st);
 
-/* ---- other Laplacian-system centralities (Sec. 2) ------------------------ */
+/* ---- other Laplacian-system centralities (Sec. 3.2) ------------------------ */
 
 /* Spanning-edge centrality of ne edges {u_i, v_i} of the loaded graph: the
  * weighted share of spanning trees that contain the edge, equal to
@@ -337,7 +337,7 @@ int cfc_spanning_edge_jl(cfc_graph* g, int64_t ne, const int64_t* u, const int64
 int cfc_current_throughput(cfc_graph* g, int64_t npairs, const int64_t* s,
                            const int64_t* t, double* tau,
                            const cfc_solve_params* p, cfc_solve_stats* st);
-/* Current-flow betweenness (Brandes and Fleischer; named in Sec. 2) of every
+/* Current-flow betweenness (Brandes and Fleischer; named in Sec. 3.2) of every
  * node: the mean throughput over the unordered pairs {s, t} of V \ {v},
  * c_CB(v) = sum tau_st(v) / C(n-1, 2).  cfc_cfb_exact solves all C(n, 2)
  * pairs (small graphs); cfc_cfb_sampled draws `count` ordered pairs with
@@ -406,8 +406,11 @@ typedef struct {
 
 int cfc_server_create(cfc_ctx* ctx, const cfc_server_opts* opts, cfc_server** out);
 /* Register a graph whose hierarchy is built; builds its sketch if jl_k > 0.
- * The graph must outlive the server and must not be used elsewhere while
- * the server runs. */
+ * From then until cfc_server_destroy the server's worker thread owns the
+ * graph's device state: every direct call on the graph (cfc_solve, the
+ * estimators, cfc_hierarchy_build, ...) returns CFC_E_STATE, and a graph can
+ * be registered with one server at a time (CFC_E_STATE otherwise).  The
+ * graph must outlive the server. */
 int cfc_server_add_graph(cfc_server* s, cfc_graph* g, int32_t* gid);
 /* Queue a query; returns at once with a ticket (CFC_E_BUSY if full). */
 int cfc_server_submit(cfc_server* s, const cfc_query* q, uint64_t* ticket);

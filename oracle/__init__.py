@@ -15,6 +15,12 @@ Laplacian Solver" (arXiv 1607.02955) that it writes out:
   by conjugate gradients (Sec. 3.1); electrical farness and c_ER (Eq. 3).
 * ``estimators`` -- the Sampling estimator (Sec. 5.1, Prop. 1) and the
   projection (JLT) estimator (Sec. 5.2, Algorithm 1).
+* ``spectral``   -- d_ER on the undeleted N x M grid from the Laplacian's
+  cosine eigenbasis (Sec. 5.2's d_ER = (e_u - e_v)^T L^+ (e_u - e_v) written
+  out in that basis), which pins solves on grids too large for the dense
+  routes.
+* ``edges``, ``betweenness`` -- spanning-edge centrality and current-flow
+  betweenness (named in Sec. 3.2).
 * ``rng``        -- the counter-based generator that fixes pivots and
   projection signs for a seed (SplitMix64, Lemire's bounded integers, Floyd's
   subset sampling), written from the published definitions.

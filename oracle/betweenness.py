@@ -1,4 +1,4 @@
-"""Current-flow betweenness (Sec. 2, last paragraph: Brandes and Fleischer).
+"""Current-flow betweenness (Sec. 3.2, last paragraph: Brandes and Fleischer).
 
 The paper names current-flow betweenness next to current-flow closeness as
 the two centralities of the electrical-network view.  Its definition, in the

@@ -1,4 +1,4 @@
-"""Spanning-edge centrality (Sec. 2, Laplacian systems in network analysis).
+"""Spanning-edge centrality (Sec. 3.2, Laplacian systems in network analysis).
 
 The paper names spanning-edge centrality (Mavroforakis et al., 2015) as one
 of the measures computed from Laplacian systems.  Its definition: the share

@@ -416,9 +416,18 @@ class Server:
         return s.as_dict()
 
     def close(self):
+        """Stop the workers (after the refinement step each is in) and give
+        the graphs back to direct calls."""
         if getattr(self, "handle", None):
             lib().cfc_server_destroy(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

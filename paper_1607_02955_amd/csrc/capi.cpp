@@ -92,7 +92,14 @@ struct cfc_ctx : Ctx {};
 static Graph* G(cfc_graph* g) { return reinterpret_cast<Graph*>(g); }
 static const Graph* G(const cfc_graph* g) { return reinterpret_cast<const Graph*>(g); }
 
+// A graph registered with a server is served by that server's worker
+// thread alone until the server is destroyed.
+static void not_served(const Graph* g) {
+  if (g->server.load()) fail(CFC_E_STATE, "graph is registered with a server (destroy the server first)");
+}
+
 static void need_device(Graph* g) {
+  not_served(g);
   if (g->ctx->host_only()) fail(CFC_E_STATE, "context has no device");
   if (!g->D) fail(CFC_E_STATE, "hierarchy not built (call cfc_hierarchy_build)");
   CFC_HIP(hipSetDevice(g->ctx->device));
@@ -204,6 +211,7 @@ int cfc_hierarchy_build(cfc_graph* gg, const cfc_setup_params* p) {
   if (!gg) fail(CFC_E_INVALID, "graph is NULL");
   Graph* g = G(gg);
   std::lock_guard<std::mutex> lk(g->mu);
+  not_served(g);
   build_hierarchy(*g, p ? *p : default_setup());
   g->tuned.clear();
   if (!g->ctx->host_only()) upload_hierarchy(*g);

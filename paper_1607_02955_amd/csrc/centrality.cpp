@@ -1,9 +1,9 @@
 // Further uses of the batched Laplacian solve:
 //   shared-pivot Sampling -- one pivot set for every query node (Sec. 5.1
 //                            read literally), k + q solves instead of k q;
-//   spanning-edge centrality -- w_e d_ER(u, v) (Sec. 2), exact or from the
+//   spanning-edge centrality -- w_e d_ER(u, v) (Sec. 3.2), exact or from the
 //                            projection sketch of Sec. 5.2;
-//   current-flow betweenness -- node throughput of unit s-t currents (Sec. 2,
+//   current-flow betweenness -- node throughput of unit s-t currents (Sec. 3.2,
 //                            electrical networks), summed over pairs.
 #include <algorithm>
 #include <cmath>

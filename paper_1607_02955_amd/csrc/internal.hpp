@@ -156,6 +156,10 @@ struct Graph {
   // autotuned (precision, requested W or 0, W, depth, one-step refinement)
   std::vector<std::array<int, 5>> tuned;
   std::mutex mu;
+  // Server this graph is registered with (null when none).  While it is
+  // set, the server's worker thread is the only user of the graph's device
+  // state (workspaces, sketch), and direct calls are refused.
+  std::atomic<const void*> server{nullptr};
   Graph();
   ~Graph();
 };

@@ -330,8 +330,20 @@ int cfc_server_add_graph(cfc_server* s, cfc_graph* gh, int32_t* gid) {
   try {
     if (!s || !gh) fail(CFC_E_INVALID, "NULL argument");
     Graph* g = GG(gh);
+    // direct calls on the graph hold g->mu; once the server is recorded they
+    // are refused, so from here on only this call and then the worker
+    // thread touch the graph's device state
+    std::lock_guard<std::mutex> glk(g->mu);
     if (!g->D) fail(CFC_E_STATE, "hierarchy not built");
     if (g->ctx != s->ctx) fail(CFC_E_INVALID, "graph belongs to another context");
+    const void* none = nullptr;
+    if (!g->server.compare_exchange_strong(none, static_cast<const void*>(s)))
+      fail(CFC_E_STATE, "graph is already registered with a server");
+    struct Release {  // undo the claim if registration fails below
+      Graph* g;
+      bool keep = false;
+      ~Release() { if (!keep) g->server.store(nullptr); }
+    } rel{g};
     CFC_HIP(hipSetDevice(s->ctx->device));
     if (s->opts.jl_k > 0 && !(g->jl.valid && g->jl.k == s->opts.jl_k && g->jl.seed == s->opts.seed)) {
       cfc_solve_params p = default_solve();
@@ -357,6 +369,7 @@ int cfc_server_add_graph(cfc_server* s, cfc_graph* gh, int32_t* gid) {
       w->gid = (int)s->graphs.size();
       s->graphs.push_back(std::move(w));
     }
+    rel.keep = true;
     wp->th = std::thread([wp] { wp->run(); });
     if (gid) *gid = wp->gid;
     return CFC_OK;
@@ -545,6 +558,7 @@ void cfc_server_destroy(cfc_server* s) {
       (void)hipStreamSynchronize(w->stream);
       (void)hipStreamDestroy(w->stream);
     }
+    w->g->server.store(nullptr);  // direct calls are allowed again
   }
   delete s;
 }

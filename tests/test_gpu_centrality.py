@@ -217,3 +217,40 @@ def test_locality_orders_same_resistances(ctx, order):
     t = rng.integers(0, eg.n, 100)
     Rm = R.resistance_matrix(R.pinv(LAP.of(eg, dense=True)))
     np.testing.assert_allclose(g.resistance(s, t, tol=1e-10, precision=1), Rm[s, t], rtol=1e-8, atol=1e-12)
+
+
+# ---- the same estimators at the benchmark tolerance ----------------------------
+
+@pytest.mark.parametrize("kind", ["shared", "all_node_jl", "spanning_jl", "cfb"])
+def test_estimators_at_bench_tolerance(ctx, kind):
+    """At the solve tolerance the benchmarks run (1e-6, mixed precision, the
+    autotuned cycle) every estimator matches the oracle's (same seed,
+    solves to 1e-12) to <= 1e-4 relative."""
+    print(f"case: {kind} at tol 1e-6", flush=True)
+    if kind == "shared":
+        eg = synth.barabasi_albert(4000, 4, seed=31)
+        nodes = synth.query_nodes(eg.n, 12, seed=2)
+        g = load(ctx, eg)
+        got, _, st = g.farness_sampling_shared(nodes, 300, 5, stats=True, tol=1e-6)
+        want, _, _ = E.sampling_shared(LAP.of(eg), eg, nodes, 300, 5, tol=1e-12)
+    elif kind == "all_node_jl":
+        eg = synth.road_grid(60, seed=4)
+        g = load(ctx, eg)
+        st = g.jl_sketch(128, seed=6, tol=1e-6, stats=True)
+        got, _ = g.farness_jl()
+        want, _, _ = E.projection(LAP.of(eg), eg, np.arange(eg.n), 128, 6, tol=1e-12)
+    elif kind == "spanning_jl":
+        eg = hubbed(n=3000, m=9000, hubs=1, hub_deg=800, seed=13)
+        g = load(ctx, eg)
+        got, st = g.spanning_edge_jl(eg.u, eg.v, 128, seed=9, stats=True, tol=1e-6)
+        want = SE.spanning_edge_jl(LAP.of(eg), eg, eg.u, eg.v, 128, 9, tol=1e-12)
+    else:
+        eg = synth.barabasi_albert(2500, 4, seed=33)
+        g = load(ctx, eg)
+        got, st = g.cfb_sampled(700, seed=8, stats=True, tol=1e-6)
+        want = CB.cfb_sampled(LAP.of(eg), eg, 700, 8, tol=1e-12)
+    scale = np.abs(want).max()
+    err = np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * scale))
+    say(kind, "max rel err vs oracle", err, "max rel residual", st["max_rel_residual"])
+    assert st["max_rel_residual"] <= 1e-6
+    assert err <= 1e-4

@@ -179,7 +179,7 @@ def test_tiny_graph_single_level(hctx):
     np.testing.assert_allclose(lv["coarse_pinv"], R.pinv(_level_laplacian(lv)), atol=1e-12)
 
 
-def test_setup_param_errors(hctx):
+def test_setup_param_errors_ranges(hctx):
     g = cfc.Graph.from_edgelist(hctx, synth.grid(8))
     with pytest.raises(cfc.CfcError):
         g.build_hierarchy(mu=2.5)
@@ -248,7 +248,7 @@ def test_locality_orders_give_valid_nested_hierarchies(hctx, order):
         assert deg[np.argsort(p)[0]] == deg.max()
 
 
-def test_setup_param_errors(hctx):
+def test_setup_param_errors_enums(hctx):
     eg = synth.path_graph(10)
     g = cfc.Graph.from_edgelist(hctx, eg)
     for kw in ({"order": 4}, {"eliminate": 3}, {"device": 2}):

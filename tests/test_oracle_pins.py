@@ -197,6 +197,22 @@ def test_grid32_corner_farness_all_routes():
     assert abs(R.farness_dense(Lp, 5 * 32 + 9)[0] / grid_spectral_farness(32, 5, 9) - 1) < 1e-11
 
 
+def test_grounded_sparse_matches_dense_and_closed_forms():
+    # weighted graph: against the dense pseudoinverse, for every choice of ground
+    g = synth.random_connected(60, 200, seed=4)
+    Lp = R.pinv(LAP.of(g, dense=True))
+    rng = np.random.default_rng(6)
+    s, t = rng.integers(0, 60, 30), rng.integers(0, 60, 30)
+    for gnd in (0, int(s[0]), 59):
+        np.testing.assert_allclose(R.resistance_grounded_sparse(LAP.of(g), s, t, gnd),
+                                   R.resistance_from_inverse(Lp, s, t), atol=1e-12)
+    # path: distance; cycle: d (n - d) / n
+    np.testing.assert_allclose(R.resistance_grounded_sparse(LAP.of(synth.path_graph(9)), [0, 2], [8, 7]),
+                               [8.0, 5.0], atol=1e-12)
+    np.testing.assert_allclose(R.resistance_grounded_sparse(LAP.of(synth.cycle_graph(10)), [0], [3], 5),
+                               [3 * 7 / 10], atol=1e-12)
+
+
 def test_cg_matches_dense_on_weighted_graph():
     g = synth.random_connected(60, 200, seed=5)
     L, Lp, _ = dense_routes(g)
