@@ -314,6 +314,19 @@ int cfc_farness_sampling_shared(cfc_graph* g, int64_t q, const int64_t* nodes,
                                 int64_t k, uint64_t seed, double* far, double* clo,
                                 const cfc_solve_params* p, cfc_solve_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * projection farness and closeness as cfc_farness_jl, computed without any
+ * allocation.  The node ids and both outputs are staged in a fixed device
+ * array of 6 MiB per GPU (set up when a context is created on that GPU and
+ * held until the process ends), so q <= 262144 nodes per call (CFC_E_INVALID
+ * above that).  nodes: host or device int64[q], or NULL with q = n for every
+ * node; far, clo (clo may be NULL): host or device double[q].  Calls on one
+ * GPU share its staging array: calls that overlap on one GPU race.  Same
+ * errors as cfc_farness_jl; node ids are range-checked on the device, and
+ * after CFC_E_INVALID for a bad id the outputs hold NaN where ids were bad. */
+int cfc_farness_jl_static(cfc_graph* g, int64_t q, const int64_t* nodes, double* far, double* clo);
+
 /* ---- other Laplacian-system centralities (Sec. 3.2) ------------------------ */
 
 /* Spanning-edge centrality of ne edges {u_i, v_i} of the loaded graph: the

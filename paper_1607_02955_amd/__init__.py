@@ -293,6 +293,25 @@ class Graph:
                                       _p(far, C.c_double), _p(clo, C.c_double), C.byref(p), C.byref(st)))
         return (far, clo, st.as_dict()) if stats else (far, clo)
 
+    def farness_jl_static(self, nodes=None, far=None, clo=None):
+        """cfc_farness_jl_static: projection farness and closeness without
+        any device allocation (at most 262,144 nodes per call).  nodes,
+        far and clo may be numpy arrays or device tensors (int64 / float64,
+        contiguous); nodes None means every node.  Returns (far, clo)."""
+        def ptr(a):
+            return C.c_void_p(a.data_ptr()) if hasattr(a, "data_ptr") else a.ctypes.data_as(C.c_void_p)
+        if nodes is None:
+            q, np_nodes = self.n, None
+        else:
+            if not hasattr(nodes, "data_ptr"):
+                nodes = _i64(nodes).ravel()
+            q, np_nodes = int(nodes.shape[0]), nodes
+        far = np.empty(q) if far is None else far
+        clo = np.empty(q) if clo is None else clo
+        check(lib().cfc_farness_jl_static(self.handle, q, None if np_nodes is None else ptr(np_nodes),
+                                          ptr(far), ptr(clo)))
+        return far, clo
+
     def farness_sampling(self, nodes, k, seed=1, stats=False, **kw):
         nodes = _i64(nodes).ravel()
         far, clo = np.empty(nodes.shape[0]), np.empty(nodes.shape[0])

@@ -130,6 +130,7 @@ int cfc_ctx_create(const cfc_ctx_opts* o, cfc_ctx** out) {
     CFC_HIP(hipGetDeviceCount(&nd));
     if (c->device >= nd) fail(CFC_E_INVALID, "no such device");
     CFC_HIP(hipSetDevice(c->device));
+    noalloc_init(c->device);
     if (o && o->stream) {
       c->stream = static_cast<hipStream_t>(o->stream);
     } else {

@@ -171,6 +171,9 @@ Graph* load_graph(Ctx* ctx, int64_t n, int64_t m, const int64_t* u, const int64_
 void build_hierarchy(Graph& g, const cfc_setup_params& p);
 void upload_hierarchy(Graph& g);
 cfc_setup_params default_setup();
+// noalloc.hip: look up this device's copy of the static staging array of
+// cfc_farness_jl_static (the device must be current)
+void noalloc_init(int device);
 // rng host helpers
 void sampling_pivots(uint64_t seed, int64_t node, int64_t n, int64_t k, std::vector<int64_t>& out);
 
