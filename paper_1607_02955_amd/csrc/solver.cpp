@@ -345,24 +345,26 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   const double nw = (double)w.W * es;
   const DevLevel& d0 = g->D->lv[0];
   const void* rsrc = update ? r_out : r_in;
-  if (L == 1 && !exact) {
-    // depth one: Jacobi-preconditioned CG, z = S r
+  if ((L == 1 && !exact) || schur) {
+    // depth one: Jacobi-preconditioned CG on the base level, z = S r
+    const DevLevel& db = g->D->lv[base];
+    const LevelArgs& lb = w.la[base];
     if (update) {
       prof_begin(K_RESTRICT0);
-      k.update_jacobi(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, bfz ? w.z.p : nullptr,
+      k.update_jacobi(lb, r_in, w.q.p, w.p.p, w.x.p, r_out, bfz ? w.z.p : nullptr,
                       w.scal.as<double>(), first_x, w.part_ptr(P_RR), w.part_ptr(P_CS),
                       w.part_ptr(P_RZ), bfz ? 1 : 0, xfu ? 1 : 0, s);
-      const double ub = d0.n * nw * upd_blocks(first_x) + 2.0 * es * d0.n + (bfz ? 2.0 * d0.n * w.W : 0.0);
+      const double ub = db.n * nw * upd_blocks(first_x) + 2.0 * es * db.n + (bfz ? 2.0 * db.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
-      g_rr = grid_for(d0.n, k.rg);
+      g_rr = grid_for(db.n, k.rg);
       g_cs = xfu ? 0 : g_rr;  // with xfu the sums of x come with the last update
     } else {
       // r . S r (and the bfloat16 copy of z = S r when the product gathers it)
-      k.jacobi(w.la[0], r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), bfz ? 1 : 0, s);
-      bytes += d0.n * nw + es * d0.n + (bfz ? 2.0 * d0.n * w.W : 0.0);
+      k.jacobi(lb, r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), bfz ? 1 : 0, s);
+      bytes += db.n * nw + es * db.n + (bfz ? 2.0 * db.n * w.W : 0.0);
     }
-    g_rz = grid_for(d0.n, k.rg);
+    g_rz = grid_for(db.n, k.rg);
     return;
   }
   if (d0.nC > 0 && L >= 2) {
@@ -541,15 +543,15 @@ void Solver::read_scal(int which, double* out) {
 void Solver::iteration(bool first, void* r_in, void* r_out) {
   Workspace& w = *ws;
   const KernTable& k = *w.kt;
-  const DevLevel& d0 = g->D->lv[0];
+  const DevLevel& d0 = g->D->lv[base];
   const size_t es = w.fp64 ? 8 : 4;
   const double nw = (double)w.W * es;
   const int W = w.W;
   prof_begin(K_SPMM);
   // depth one: z = S r_in is formed inside the product kernel
   // (or gathered from its bfloat16 copy in ws.z)
-  const bool jac = nuse == 1 && w.nlev > 1;
-  k.spmm_pq(w.la[0], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, xfu ? w.x.p : nullptr,
+  const bool jac = (nuse == 1 && w.nlev > 1) || schur;
+  k.spmm_pq(w.la[base], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, xfu ? w.x.p : nullptr,
             w.scal.as<double>(), first, w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
   const double sb = (bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
                          : d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) +
@@ -557,7 +559,7 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
                     (xfu && !first ? 2.0 * d0.n * nw : 0.0);
   prof_end(K_SPMM, sb);
   bytes += sb;
-  finalize(W, F_ALPHA, k.rows_grid(w.la[0], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
+  finalize(W, F_ALPHA, k.rows_grid(w.la[base], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
            w.scal.as<double>(), stream);
   vcycle(true, first, r_in, r_out);
   finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
@@ -584,16 +586,55 @@ void Solver::capture_pair() {
 // between ws.rb and ws.ra; with use_graph the later iterations replay a
 // captured pair of iterations.
 int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every) {
-  const int it = pcg_iterations(rr0, inner_tol, max_inner, check_every);
-  if (xfu) {
-    // the product kernels applied every x update but the last one
-    Workspace& w = *ws;
-    const DevLevel& d0 = g->D->lv[0];
-    const int gcs = grid_for(d0.n, w.kt->rg);
-    w.kt->xfinal(d0.n, w.x.p, w.p.p, w.scal.as<double>(), w.part_ptr(P_CS), stream);
-    finalize(w.W, F_CS, gcs, w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
-    bytes += 3.0 * d0.n * w.W * (w.fp64 ? 8 : 4);
+  Workspace& w = *ws;
+  const KernTable& k = *w.kt;
+  const double es = w.fp64 ? 8 : 4;
+  if (!schur) {
+    r0 = w.ra.p;
+    const int it = pcg_iterations(rr0, inner_tol, max_inner, check_every);
+    if (xfu) {
+      // the product kernels applied every x update but the last one
+      const DevLevel& d0 = g->D->lv[0];
+      const int gcs = grid_for(d0.n, k.rg);
+      k.xfinal(d0.n, w.x.p, w.p.p, w.scal.as<double>(), w.part_ptr(P_CS), stream);
+      finalize(w.W, F_CS, gcs, w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
+      bytes += 3.0 * d0.n * w.W * es;
+    }
+    return it;
   }
+  // Schur mode.  With the kept rows C first and the eliminated rows F an
+  // independent set, L d = r is L_CC d_C + L_CF d_F = r_C, L_FC d_C + D_F d_F
+  // = r_F, so d_C solves S d_C = t_C with t_C = r_C - L_CF D_F^-1 r_F
+  // (t_c = r_c + sum_f w_cf / d_f r_f) and d_F = D_F^-1 (r_F - L_FC d_C).
+  const DevLevel& d0 = g->D->lv[0];
+  const DevLevel& fw = g->D->fwd;
+  const int n = d0.n, nc = d0.nC;
+  if (!w.rt.p) w.rt.alloc(g->ctx, (size_t)nc * w.W * (size_t)es);
+  k.elim_fwd(w.lf, w.ra.p, w.rt.p, nullptr, nullptr, 0, stream);
+  bytes += 2.0 * nc * w.W * es + (double)(n - nc) * w.W * es + 8.0 * fw.nnz + 4.0 * nc;
+  // the inner tolerance is relative to the folded residual
+  k.dot(nc, w.rt.p, w.rt.p, w.part_ptr(P_RR), stream);
+  finalize(w.W, F_R64, grid_for(nc, k.rg), w.part_ptr(P_RR), 0, nullptr, 0, nullptr, w.scal.as<double>(),
+           stream, w.mirror_dev);
+  std::vector<double> rrt(w.W);
+  read_scal(S_R64, rrt.data());
+  for (int j = 0; j < w.W; ++j)
+    if (!(rr0[j] > 0)) rrt[j] = 0;  // columns the caller left out stay out
+  bytes += nc * w.W * es;
+  r0 = w.rt.p;
+  const int it = pcg_iterations(rrt, inner_tol, max_inner, check_every);
+  if (xfu) {
+    k.xfinal(nc, w.x.p, w.p.p, w.scal.as<double>(), w.part_ptr(P_CS), stream);
+    bytes += 3.0 * nc * w.W * es;
+  }
+  // d_F from d_C (ws.x's first nc rows) and r_F (rows nc.. of ws.ra, which
+  // the level-1 iterations never touch), then the column sums of d over all
+  // rows for the mean projection
+  k.elim_back(w.la[0], w.ra.p, w.x.p, w.part_ptr(P_RZ), 0, 0, stream);
+  k.dot(n, w.x.p, nullptr, w.part_ptr(P_CS), stream);
+  finalize(w.W, F_CS, grid_for(n, k.rg), w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(),
+           stream);
+  bytes += (n - nc) * (double)w.W * es * 2 + 2.0 * (n - nc) * w.W * es + 16.0 * (n - nc) + n * (double)w.W * es;
   return it;
 }
 
@@ -601,7 +642,7 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
                            int check_every) {
   Workspace& w = *ws;
   const int W = w.W;
-  vcycle(false, false, w.ra.p, nullptr);
+  vcycle(false, false, r0, nullptr);
   finalize(W, F_RZINIT, g_rz, w.part_ptr(P_RZ), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
   std::vector<double> rr(W);
   const double tol2 = inner_tol * inner_tol;
@@ -615,7 +656,7 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
     return true;
   };
   int it = 1;
-  iteration(true, w.ra.p, w.rb.p);
+  iteration(true, r0, w.rb.p);
   if (max_inner == 1 || (1 % check_every == 0 && converged())) return it;
   if (params.use_graph) {
     if (!gexec) capture_pair();
@@ -754,6 +795,12 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   const char* bz = std::getenv("CFC_BF16_Z");
   const bool jac1 = nuse == 1 && ws->nlev > 1;
   const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && ws->nlev > 2;
+  // An elimination level with one Jacobi step behind it: CG on the Schur
+  // complement (CFC_SCHUR=0 keeps CG on level 0 with the elimination inside
+  // the preconditioner).
+  const char* sc = std::getenv("CFC_SCHUR");
+  schur = elim2 && !(sc && sc[0] == '0');
+  base = schur ? 1 : 0;
   bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
   // The product kernel carries the x updates (CFC_FUSE_X=0 keeps them in
   // the update kernel).

@@ -26,6 +26,7 @@ struct Workspace {
   DBuf x64;                   // FP64 solution block
   DBuf rhs;                   // FP64 dense right-hand sides (on demand)
   DBuf r64;                   // FP64 residual kept between refinement steps (on demand)
+  DBuf rt;                    // Schur mode: the residual folded onto the kept rows
   DBuf pairs;                 // int32 ps[W], pt[W], segment bounds
   DBuf part;                  // FP64 partial sums [P_COUNT][kMaxGrid][W]
   DBuf scal;                  // FP64 per-column scalars [S_N][W]
@@ -48,6 +49,13 @@ struct Solver {
   int g_rz = 0, g_rr = 0, g_cs = 0;
   int nuse = 1;  // V-cycle depth
   bool bfz = false;  // Jacobi paths: z = M^-1 r stored as bfloat16 in ws->z
+  // Schur mode (an elimination level with one Jacobi step behind it): the
+  // inner CG runs on level 1, the Schur complement S, preconditioned by one
+  // Jacobi step; pcg() folds the level-0 residual onto the kept rows first
+  // and back-substitutes the eliminated rows of the correction after.
+  bool schur = false;
+  int base = 0;  // level the inner CG runs on (1 in Schur mode)
+  void* r0 = nullptr;  // the inner CG's initial residual (ws.ra, or ws.rt in Schur mode)
   bool xfu = false;  // x updates applied by the product kernel
   bool multi_step = false;  // a block of this solve took more than one refinement step
   // FP32/FP64 blocks streamed by the level-0 CG update (r_in, q, x, p read;

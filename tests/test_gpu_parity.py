@@ -342,6 +342,33 @@ def test_elimination_level_all_depths(ctx, W, prec):
     np.testing.assert_allclose(r_g, Rm[s, t], rtol=10 * tol, atol=1e-12)
 
 
+@pytest.mark.parametrize("W", [64, 256])
+def test_schur_cg_matches_level0_cg(ctx, W, monkeypatch):
+    """An elimination level with one Jacobi step behind it: CG on the Schur
+    complement (the residual folded onto the kept rows, the eliminated rows
+    back-substituted) and CG on level 0 with the elimination inside the
+    preconditioner give the oracle's resistances in about as many
+    iterations, also on an R-MAT graph whose hubs are heavy rows of the
+    Schur complement, and with the iterations replayed from a HIP graph."""
+    for name, eg in [("leafy", leafy_graph(seed=W + 1)), ("rmat", synth.rmat(11, seed=W))]:
+        g = load(ctx, eg, coarsest_max=64, eliminate=2)
+        assert g.info()["eliminated"] > 0
+        _, Rm = dense_R(eg)
+        rng = np.random.default_rng(W)
+        s = rng.integers(0, eg.n, 2 * W + 5)
+        t = rng.integers(0, eg.n, 2 * W + 5)
+        its = {}
+        for mode in ("1", "0"):
+            monkeypatch.setenv("CFC_SCHUR", mode)
+            for graph in (0, 1):
+                r, st = g.resistance(s, t, block=W, tol=1e-8, levels=2, use_graph=graph, stats=True,
+                                     max_inner=3000)
+                say("schur", name, W, mode, graph, st["inner_iters"], st["refine_steps"], st["max_rel_residual"])
+                np.testing.assert_allclose(r, Rm[s, t], rtol=1e-7, atol=1e-12)
+                its[mode, graph] = st["inner_iters"]
+        assert its["1", 0] <= 1.25 * its["0", 0] + 4, its
+
+
 @pytest.mark.parametrize("case", ["depth1_hubs", "elim_depth2"])
 def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
     """The bfloat16 copy of z = M^-1 r (depth one, or elimination plus one
