@@ -351,6 +351,8 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--levels", type=int, default=0, help="V-cycle depth (0 = autotuned)")
+    ap.add_argument("--order", type=int, default=0,
+                    help="locality order of the hierarchy: 0 auto, 1 Cuthill-McKee, 2 input, 3 hubs first")
     ap.add_argument("--eliminate", type=int, default=1,
                     help="low-degree elimination level: 0 off, 1 when >= 5%% of nodes qualify, 2 always")
     ap.add_argument("--block", type=int, default=-1, help="block width W (default: the workload's)")
@@ -439,7 +441,7 @@ def measure(workload, args, extras=True, ctx=None):
     ctx = ctx or cfc.Context(0)
     g = cfc.Graph.from_edgelist(ctx, eg)
     t0 = time.perf_counter()
-    g.build_hierarchy(eliminate=args.eliminate)
+    g.build_hierarchy(eliminate=args.eliminate, order=args.order)
     setup_s = time.perf_counter() - t0
     info = g.info()
     progress(f"hierarchy: {info['levels']} levels, {info['eliminated']} eliminated, {setup_s:.1f} s")

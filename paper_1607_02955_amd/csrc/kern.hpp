@@ -37,6 +37,11 @@ struct LevelArgs {
   const int* seg_e = nullptr;  // [nseg+1] edge range of each segment
   const int* seg_row = nullptr;// [nseg] row of each segment
   void* hpart = nullptr;       // [nseg][W] partial sums (element type T)
+  // [nheavy][W] (element type T): the segment partials of each heavy row
+  // added in segment order by a row-parallel pass after the pre-pass, so
+  // the main kernels read one row per heavy row (nullptr: they add the
+  // segments themselves)
+  void* hsum = nullptr;
   // Elimination level (nC > 0): rows [nC, n) are eliminated; row nC + i has
   // kept neighbours enb[2i], enb[2i+1] (-1 = none), conductances ew[2i..]
   // and einv[i] = 1 / D_ii (element type T).

@@ -3,10 +3,12 @@
 // Data layout: every n x W block is node-major (node u's W values are
 // contiguous).  The W columns are split into NS slices of WS = W / NS
 // columns and workgroup b works on slice b mod NS: the hardware deals
-// workgroups to the 8 XCDs round-robin, so with NS = 8 each XCD touches only
-// its own column slice of every gathered row and its private L2 holds 1/8 of
-// the block (narrower blocks use fewer, 32-column slices).  Inside a slice a "row group" of LPR lanes owns one row at a
-// time, each lane V consecutive columns (WS = LPR * V), so a neighbour's
+// workgroups to the 8 XCDs round-robin, so each XCD touches only its own
+// column slice of every gathered row and its private L2 holds 1/NS of the
+// block (8 slices of 64 columns at W = 512, 4 at W = 256 with two XCDs per
+// slice, 32-column slices below).  Inside a slice a "row group" of LPR
+// lanes owns one row at a time, each lane V consecutive columns
+// (WS = LPR * V), so a neighbour's
 // slice row is one coalesced WS*sizeof(T)-byte read.  The row groups of a
 // workgroup walk a contiguous range of row tiles.
 //
@@ -29,9 +31,13 @@ namespace dev {
 
 // Column slicing and lane shape of a W-wide block.
 template <int W> struct Shape {
-  // column slices: at most one per XCD, each at least 32 columns wide so a
-  // slice row (>= 128 B in FP32) fills whole cache lines
-  static constexpr int NS = W >= 256 ? 8 : (W >= 32 ? W / 32 : 1);
+  // column slices: at most one per XCD, 32 columns wide up to W = 128 (a
+  // slice row of >= 128 B in FP32 fills whole cache lines) and 64 columns
+  // from W = 256, so that the bfloat16 rows the operator product gathers
+  // are 128 B too: on R-MAT-20 at W = 256, 4 slices of 64 columns measured
+  // 3.05 ms per product against 3.98 ms for 8 slices of 32 (random 64-byte
+  // reads use HBM worse than 128-byte ones)
+  static constexpr int NS = W >= 512 ? 8 : (W >= 256 ? 4 : (W >= 32 ? W / 32 : 1));
   static constexpr int WS = W / NS;           // columns per slice
   static constexpr int V = WS >= 4 ? 4 : 1;   // columns per lane
   static constexpr int LPR = WS / V;          // lanes per row group
@@ -231,6 +237,12 @@ __device__ __forceinline__ void add_heavy(const LevelArgs& L, int u, T* nb, int 
   const int h = L.heavy[u];
   if (h < 0) return;
   constexpr int V = Shape<W>::V;
+  if (L.hsum) {
+    const Vec<T, V> x = ld<T, V>(static_cast<const T*>(L.hsum) + (size_t)h * W + c0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) nb[i] += x.v[i];
+    return;
+  }
   const T* hp = static_cast<const T*>(L.hpart);
   for (int sgi = L.hseg[h]; sgi < L.hseg[h + 1]; ++sgi) {
     const Vec<T, V> x = ld<T, V>(hp + (size_t)sgi * W + c0);
@@ -301,6 +313,50 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
       for (int i = 0; i < V; ++i) o.v[i] = nb[i];
       st<T, V>(static_cast<T*>(L.hpart) + (size_t)sgi * W + c0, o);
     }
+  }
+}
+
+// hsum[h] = the segment partials of heavy row h added in segment order, one
+// row group per heavy row with 8 partials in flight (the largest rows have
+// hundreds of segments; left to the main kernels, the row groups that hold
+// them would set those kernels' duration).
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_heavy_sum(LevelArgs L) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  constexpr int D = 8;
+  int slice, rb, grb;
+  slice_of_block<W>(slice, rb, grb);
+  const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
+  const T* hp = static_cast<const T*>(L.hpart);
+  // strided rows: the longest rows (first in a hubs-first order) spread over
+  // the workgroups
+  const int ntiles = (L.nheavy + RG - 1) / RG;
+  for (int t = rb; t < ntiles; t += grb) {
+    const int h = t * RG + rg;
+    if (h >= L.nheavy) continue;
+    T s[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) s[i] = 0;
+    const int k1 = L.hseg[h + 1];
+    int k = L.hseg[h];
+    for (; k + D <= k1; k += D) {
+      Vec<T, V> x[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[j] = ld<T, V>(hp + (size_t)(k + j) * W + c0);
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int i = 0; i < V; ++i) s[i] += x[j].v[i];
+    }
+    for (; k < k1; ++k) {
+      const Vec<T, V> x = ld<T, V>(hp + (size_t)k * W + c0);
+#pragma unroll
+      for (int i = 0; i < V; ++i) s[i] += x.v[i];
+    }
+    Vec<T, V> o;
+#pragma unroll
+    for (int i = 0; i < V; ++i) o.v[i] = s[i];
+    st<T, V>(static_cast<T*>(L.hsum) + (size_t)h * W + c0, o);
   }
 }
 
@@ -1316,6 +1372,13 @@ struct Launch {
       hipLaunchKernelGGL((K<__VA_ARGS__, 1>), dim3(g_ * NS), dim3(kBlock), 0, s, ARGS);        \
   } while (0)
 
+  // the per-row sums of the segment partials (when the level has hsum)
+  template <typename TT>
+  static void heavy_sum(const LevelArgs& L, hipStream_t s) {
+    if (!L.nseg || !L.hsum) return;
+    const int g = std::min((L.nheavy + RG - 1) / RG, kMaxGrid);
+    hipLaunchKernelGGL((k_heavy_sum<TT, W>), dim3(g * NS), dim3(kBlock), 0, s, L);
+  }
   template <int KIND>
   static void heavy(const LevelArgs& L, const void* a, const void* q, const void* xc,
                     const double* scal, hipStream_t s) {
@@ -1323,6 +1386,7 @@ struct Launch {
     const int g = std::min(L.nseg, 4 * kMaxGrid);
     hipLaunchKernelGGL((k_heavy<T, W, KIND>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)a,
                        (const T*)q, (const T*)xc, scal);
+    heavy_sum<T>(L, s);
   }
 
   static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, void* x,
@@ -1433,6 +1497,7 @@ struct Launch {
     else if (x && L.nseg)
       hipLaunchKernelGGL((k_heavy<double, W, HK_RES64>), gh, dim3(kBlock), 0, s, L, (const double*)x,
                          (const double*)nullptr, (const double*)nullptr, (const double*)nullptr);
+    if (x) heavy_sum<double>(L, s);
     if (x_fp32) {
 #define ARGS L, (const float*)x, rhs, (T*)r_out, part
       CFC_LAUNCH(k_residual64, L.n, T, W, float);

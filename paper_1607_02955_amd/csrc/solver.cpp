@@ -280,17 +280,25 @@ Workspace& get_workspace(Graph& g, int W, bool fp64, hipStream_t s, Ctx* mem) {
   // segment partials of heavy rows, one region per level (FP64-sized so the
   // FP64 residual can share level 0's region)
   w.hpart.resize(L);
+  w.hsum.resize(L);
   for (int l = 0; l < L; ++l)
     if (g.D->lv[l].nseg) {
       w.hpart[l].alloc(c, (size_t)g.D->lv[l].nseg * W * 8);
+      w.hsum[l].alloc(c, (size_t)g.D->lv[l].nheavy * W * 8);
       w.la[l].hpart = w.hpart[l].p;
-      if (l == 0) w.la64.hpart = w.hpart[0].p;
+      w.la[l].hsum = w.hsum[l].p;
+      if (l == 0) {
+        w.la64.hpart = w.hpart[0].p;
+        w.la64.hsum = w.hsum[0].p;
+      }
     }
   if (g.D->lv[0].nC > 0) {
     w.lf = fwd_args(g, fp64);
     if (g.D->fwd.nseg) {
       w.fpart.alloc(c, (size_t)g.D->fwd.nseg * W * 8);
+      w.fsum.alloc(c, (size_t)g.D->fwd.nheavy * W * 8);
       w.lf.hpart = w.fpart.p;
+      w.lf.hsum = w.fsum.p;
     }
   }
   const size_t es = fp64 ? 8 : 4;

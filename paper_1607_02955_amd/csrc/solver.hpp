@@ -21,8 +21,9 @@ struct Workspace {
   DBuf x, ra, rb, p, q, z;    // level 0, inner element type
   std::vector<DBuf> b, xl;    // levels >= 1: right-hand side and iterate
   std::vector<DBuf> hpart;    // per level: heavy-row segment partials
+  std::vector<DBuf> hsum;     // per level: their sums per heavy row
   LevelArgs lf;               // forward operator of an elimination level 0
-  DBuf fpart;                 // its heavy-row segment partials
+  DBuf fpart, fsum;           // its heavy-row segment partials and their row sums
   DBuf x64;                   // FP64 solution block
   DBuf rhs;                   // FP64 dense right-hand sides (on demand)
   DBuf r64;                   // FP64 residual kept between refinement steps (on demand)
