@@ -220,6 +220,13 @@ void cfc_ctx_destroy(cfc_ctx* ctx);
 const char* cfc_last_error(void);
 /* Library version string. */
 const char* cfc_version(void);
+/* Bandwidth probe, not part of the method: copy `bytes` from src to dst
+ * (both device memory of the context's GPU) with the library's own
+ * streaming kernel (16-byte non-temporal loads and stores per lane) on the
+ * context's stream, and wait for it.  It is the achievable-bandwidth
+ * reference of the roofline reports and the calibration of the HBM traffic
+ * counters.  CFC_E_INVALID for NULL pointers or a host-only context. */
+int cfc_device_copy(cfc_ctx* ctx, void* dst, const void* src, size_t bytes);
 
 /* ---- graph ---------------------------------------------------------------- */
 

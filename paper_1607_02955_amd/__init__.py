@@ -146,6 +146,13 @@ class Context:
         self.device = device
         _live["ctx"].add(self)
 
+    def device_copy(self, dst, src, nbytes=None):
+        """cfc_device_copy: the library's streaming copy kernel between two
+        device tensors (a bandwidth probe; waits for the copy)."""
+        nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+        check(lib().cfc_device_copy(self.handle, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                                    nbytes))
+
     def close(self):
         if getattr(self, "handle", None):
             lib().cfc_ctx_destroy(self.handle)

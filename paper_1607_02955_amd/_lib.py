@@ -127,6 +127,7 @@ SIGNATURES = {
                                        C.POINTER(SolveParams), C.POINTER(SolveStats)]),
     "cfc_jl_sketch": (C.c_int, [vp, C.c_int64, C.c_uint64, C.POINTER(SolveParams), C.POINTER(SolveStats)]),
     "cfc_farness_jl": (C.c_int, [vp, C.c_int64, i64p, f64p, f64p]),
+    "cfc_device_copy": (C.c_int, [vp, vp, vp, C.c_size_t]),
     "cfc_farness_jl_static": (C.c_int, [vp, C.c_int64, vp, vp, vp]),
     "cfc_sampling_pivots": (C.c_int, [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, i64p]),
     "cfc_jl_sign_word": (C.c_uint64, [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64]),

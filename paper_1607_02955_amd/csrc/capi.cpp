@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "kern.hpp"
 #include "rng.hpp"
 #include "centrality.hpp"
 #include "solver.hpp"
@@ -139,6 +140,18 @@ int cfc_ctx_create(const cfc_ctx_opts* o, cfc_ctx** out) {
     }
   }
   *out = c.release();
+  return CFC_OK;
+  CFC_CATCH
+}
+
+int cfc_device_copy(cfc_ctx* c, void* dst, const void* src, size_t bytes) {
+  CFC_TRY
+  if (!c || ((!dst || !src) && bytes)) fail(CFC_E_INVALID, "NULL argument");
+  if (c->host_only()) fail(CFC_E_INVALID, "context has no device");
+  CFC_HIP(hipSetDevice(c->device));
+  stream_copy(dst, src, bytes, c->stream);
+  CFC_HIP(hipGetLastError());
+  CFC_HIP(hipStreamSynchronize(c->stream));
   return CFC_OK;
   CFC_CATCH
 }

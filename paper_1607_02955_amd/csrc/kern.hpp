@@ -167,6 +167,8 @@ void gather_rc(int64_t q, const double* src, int W, const int* row, const int* c
                hipStream_t s);
 // x64[u, j] = 0 for every row u and every column j with flag[j] != 0
 void zero_cols(int n, int W, double* x64, const int* flag, hipStream_t s);
+// plain streaming copy of `bytes` (16-byte non-temporal loads and stores)
+void stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // fill with zero bytes by a kernel (graph-capture friendly)
 void zero_fill(void* p, size_t bytes, hipStream_t s);
 // sum of x[0..n) into *out (two kernels, fixed order)

@@ -10,6 +10,8 @@
 
 namespace cfc {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 const KernTable* kern_table_1(bool);
 const KernTable* kern_table_32(bool);
 const KernTable* kern_table_64(bool);
@@ -277,6 +279,28 @@ void zero_cols(int n, int W, double* x64, const int* flag, hipStream_t s) {
   if (!total) return;
   const int g = (int)std::min<size_t>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(k_zero_cols, dim3(g), dim3(256), 0, s, n, W, x64, flag);
+}
+
+// Streaming copy: each lane moves 16 bytes per step with non-temporal loads
+// and stores, consecutive lanes on consecutive 16-byte words (every wave
+// instruction covers 1 KiB); a grid-stride loop over the 16-byte words,
+// then the tail bytes.
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                     size_t n16, const unsigned char* __restrict__ srcb,
+                                                     unsigned char* __restrict__ dstb, size_t tail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tail) dstb[t] = srcb[t];
+}
+
+void stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return;
+  const size_t n16 = bytes / 16, tail = bytes - n16 * 16;
+  const int g = (int)std::max<size_t>(1, std::min<size_t>((n16 + 255) / 256, 16384));
+  hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n16,
+                     (const unsigned char*)src + n16 * 16, (unsigned char*)dst + n16 * 16, tail);
 }
 
 void zero_fill(void* p, size_t bytes, hipStream_t s) {

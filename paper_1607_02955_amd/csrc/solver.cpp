@@ -576,17 +576,17 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
 
 void Solver::capture_pair() {
   Workspace& w = *ws;
+  const double b0 = bytes;
   const bool prof = profile;
   profile = false;  // no event records inside the captured graph
-  const double b0 = bytes;
   CFC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
   iteration(false, w.rb.p, w.ra.p);
   iteration(false, w.ra.p, w.rb.p);
   CFC_HIP(hipStreamEndCapture(stream, &graph));
+  profile = prof;
   CFC_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   pair_bytes = bytes - b0;
   bytes = b0;
-  profile = prof;
 }
 
 // Preconditioned CG on L d = r0 (r0 in ws.ra); result d in ws.x.  Returns
@@ -654,6 +654,17 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
   finalize(W, F_RZINIT, g_rz, w.part_ptr(P_RZ), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
   std::vector<double> rr(W);
   const double tol2 = inner_tol * inner_tol;
+  // no convergence test (and so no host synchronisation) before the fewest
+  // iterations an earlier block needed at this refinement step, less one
+  const std::array<int, 3> key{nuse, cur_step, (int)std::lround(4.0 * std::log10(std::max(inner_tol, 1e-300)))};
+  const auto hit = cur_step >= 0 ? w.min_its.find(key) : w.min_its.end();
+  const int first_check = hit != w.min_its.end() ? std::max(1, hit->second - 1) : 1;
+  auto record = [&](int n_it) {
+    if (cur_step < 0 || n_it >= max_inner) return n_it;  // capped runs teach nothing
+    auto ins = w.min_its.emplace(key, n_it);
+    if (!ins.second) ins.first->second = std::min(ins.first->second, n_it);
+    return n_it;
+  };
   auto converged = [&]() {
     read_scal(S_RR, rr.data());
     for (int j = 0; j < W; ++j) {
@@ -665,7 +676,7 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
   };
   int it = 1;
   iteration(true, r0, w.rb.p);
-  if (max_inner == 1 || (1 % check_every == 0 && converged())) return it;
+  if (max_inner == 1 || (first_check <= 1 && 1 % check_every == 0 && converged())) return record(it);
   if (params.use_graph) {
     if (!gexec) capture_pair();
     while (it < max_inner) {
@@ -673,9 +684,9 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
       it += 2;
       bytes += pair_bytes;
       graph_replays++;
-      if ((it / 2) % std::max(1, check_every / 2) == 0 && converged()) break;
+      if (it + 1 >= first_check && (it / 2) % std::max(1, check_every / 2) == 0 && converged()) break;
     }
-    return it;
+    return record(it);
   }
   void* ra = w.rb.p;  // current residual
   void* rb = w.ra.p;
@@ -683,9 +694,9 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
     ++it;
     iteration(false, ra, rb);
     std::swap(ra, rb);
-    if ((it % check_every == 0 || it == max_inner) && converged()) break;
+    if (it >= first_check && (it % check_every == 0 || it == max_inner) && converged()) break;
   }
-  return it;
+  return record(it);
 }
 
 // Solve one block.  rhs describes b (pairs or dense FP64 in ws.rhs, internal
@@ -762,7 +773,9 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     double itol = p.precision == CFC_PREC_FP64 ? std::max(aim * p.tol / cur_max, 1e-15)
                                                 : std::max(p.inner_tol, aim * p.tol / cur_max);
     itol = std::min(itol, 0.5);
+    cur_step = step;
     const int its = pcg(r64, itol, p.max_inner, std::max(1, p.check_every));
+    cur_step = -1;
     if (debug) std::fprintf(stderr, "[cfc]   pcg its %d (inner tol %.2e)\n", its, itol);
     inner_iters += its;
     k.xupdate64(d0.n, w.x64.as<double>(), w.x.p, w.scal.as<double>(), have_x ? 0 : 1, s);

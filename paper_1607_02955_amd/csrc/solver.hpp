@@ -1,5 +1,7 @@
 // Solver declarations.
 #pragma once
+#include <array>
+#include <map>
 #include <vector>
 
 #include "internal.hpp"
@@ -35,6 +37,9 @@ struct Workspace {
   double* pinned = nullptr;   // pinned host staging
   double* mirror = nullptr;   // host-mapped [S_N][W]: S_RR, S_R64 as finalized
   double* mirror_dev = nullptr;  // its device address
+  // fewest PCG iterations seen per (V-cycle depth, refinement step, inner
+  // tolerance in quarter decades)
+  std::map<std::array<int, 3>, int> min_its;
   ~Workspace();
   double* part_ptr(int which) const;
 };
@@ -74,6 +79,11 @@ struct Solver {
     hipEvent_t a, b;
   };
   std::vector<ProfEv> prof_ev;
+  // Refinement step of the inner solve in progress (-1: unknown); with the
+  // workspace's record of the fewest PCG iterations earlier inner solves
+  // needed at that step (same depth and inner tolerance), convergence is
+  // not tested, and the host not synchronised, before that count less one.
+  int cur_step = -1;
   double prof_ms[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0};
   int64_t prof_launches[3] = {0, 0, 0};
 
