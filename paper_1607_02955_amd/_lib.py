@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcfc.so")
+# CFC_LIB_PATH selects another build of the same sources (the sanitized
+# host build that tests/test_host_sanitized.py runs)
+LIB_PATH = os.environ.get("CFC_LIB_PATH") or os.path.join(HERE, "libcfc.so")
 
 CFC_OK = 0
 ERRORS = {
