@@ -133,7 +133,16 @@ typedef struct {
                             (default): descending degree when the largest
                             degree exceeds 32 times the mean, else the
                             Cuthill-McKee sweep */
-  int32_t pad;
+  int32_t max_complexity_pct; /* operator-complexity budget x 100: the
+                            hierarchy takes no aggregation level that would
+                            raise sum_l (nnz_l + n_l) / (nnz_0 + n_0) above
+                            it.  On expander-like complex networks the
+                            quotient graphs keep almost every edge, so the
+                            budget stops coarsening early; the deepest level
+                            then has no exact solve when it has more than
+                            4096 nodes, and every cycle ends there with one
+                            Jacobi step.  0 = default (200, i.e. 2.0),
+                            -1 = no budget (coarsen to coarsest_max) */
 } cfc_setup_params;
 
 typedef struct {

@@ -92,9 +92,12 @@ def solve_params(tol=1e-6, precision=PREC_MIXED, block=0, max_refine=20, max_inn
 
 
 def setup_params(coarsest_max=512, agg_cap=8, test_vectors=8, relax_sweeps=8, omega=0.8,
-                 mu=1.5, seed=1, eliminate=1, device=1, order=0) -> _lib.SetupParams:
+                 mu=1.5, seed=1, eliminate=1, device=1, order=0, max_complexity=0.0) -> _lib.SetupParams:
+    """max_complexity: operator-complexity budget (0 = the default 2.0, a
+    negative value = none)."""
+    pct = 0 if max_complexity == 0 else (-1 if max_complexity < 0 else int(round(100 * max_complexity)))
     return _lib.SetupParams(coarsest_max, agg_cap, test_vectors, relax_sweeps, omega, mu, seed,
-                            eliminate, device, order, 0)
+                            eliminate, device, order, pct)
 
 
 class Context:

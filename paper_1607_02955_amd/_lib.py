@@ -46,7 +46,7 @@ class SetupParams(C.Structure):
     _fields_ = [("coarsest_max", C.c_int32), ("agg_cap", C.c_int32), ("test_vectors", C.c_int32),
                 ("relax_sweeps", C.c_int32), ("omega", C.c_double), ("mu", C.c_double),
                 ("seed", C.c_uint64), ("eliminate", C.c_int32), ("device", C.c_int32),
-                ("order", C.c_int32), ("pad", C.c_int32)]
+                ("order", C.c_int32), ("max_complexity_pct", C.c_int32)]
 
 
 class SolveParams(C.Structure):

@@ -253,7 +253,7 @@ int cfc_hierarchy_level(const cfc_graph* gg, int32_t level, cfc_level_view* out)
   out->agg = h.agg.empty() ? nullptr : h.agg.data();
   out->agg_ptr = h.aggptr.empty() ? nullptr : h.aggptr.data();
   out->perm = level == 0 ? g->H.perm.data() : nullptr;
-  out->coarse_pinv = (level + 1 == (int32_t)g->H.lv.size()) ? g->H.cpinv.data() : nullptr;
+  out->coarse_pinv = (level + 1 == (int32_t)g->H.lv.size() && !g->H.cpinv.empty()) ? g->H.cpinv.data() : nullptr;
   return CFC_OK;
   CFC_CATCH
 }

@@ -171,8 +171,9 @@ void upload_hierarchy(Graph& g) {
     d.omega64 = H.omega;
     D->bytes += level_bytes(d);
   }
-  // coarsest pseudoinverse, zero-padded to a multiple of 16
-  const int nc = (int)H.lv[L - 1].n;
+  // coarsest pseudoinverse, zero-padded to a multiple of 16 (none when the
+  // complexity budget stopped coarsening on a large level)
+  const int nc = H.cpinv.empty() ? 0 : (int)H.lv[L - 1].n;
   const int ncp = (nc + 15) / 16 * 16;
   std::vector<double> P((size_t)ncp * ncp, 0.0);
   for (int i = 0; i < nc; ++i)
@@ -348,7 +349,7 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   const KernTable& k = *w.kt;
   hipStream_t s = stream;
   const int L = nuse;                 // levels this cycle visits
-  const bool exact = nuse == w.nlev;  // deepest visited level is the true coarsest
+  const bool exact = nuse == w.nlev && g->D->nc > 0;  // deepest visited level is the true coarsest
   const size_t es = w.fp64 ? 8 : 4;
   const double nw = (double)w.W * es;
   const DevLevel& d0 = g->D->lv[0];
@@ -441,7 +442,7 @@ void Solver::vcycle_elim(bool update, bool first_x, const void* r_in, void* r_ou
   const KernTable& k = *w.kt;
   hipStream_t s = stream;
   const int L = nuse;
-  const bool exact = nuse == w.nlev;
+  const bool exact = nuse == w.nlev && g->D->nc > 0;
   const size_t es = w.fp64 ? 8 : 4;
   const double nw = (double)w.W * es;
   const DevLevel& d0 = g->D->lv[0];
@@ -558,7 +559,8 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
   prof_begin(K_SPMM);
   // depth one: z = S r_in is formed inside the product kernel
   // (or gathered from its bfloat16 copy in ws.z)
-  const bool jac = (nuse == 1 && w.nlev > 1) || schur;
+  // one Jacobi step as the whole preconditioner (no exact solve on level 0)
+  const bool jac = (nuse == 1 && (w.nlev > 1 || g->D->nc == 0)) || schur;
   k.spmm_pq(w.la[base], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, xfu ? w.x.p : nullptr,
             w.scal.as<double>(), first, w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
   const double sb = (bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
@@ -814,8 +816,10 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   // complement: keep z as bfloat16 for the product's gathers (CFC_BF16_Z=0
   // keeps it FP32).
   const char* bz = std::getenv("CFC_BF16_Z");
-  const bool jac1 = nuse == 1 && ws->nlev > 1;
-  const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && ws->nlev > 2;
+  // the deepest level the cycle visits is smoothed, not solved exactly
+  const bool smoothed = nuse < ws->nlev || g->D->nc == 0;
+  const bool jac1 = nuse == 1 && smoothed;
+  const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && smoothed;
   // An elimination level with one Jacobi step behind it: CG on the Schur
   // complement (CFC_SCHUR=0 keeps CG on level 0 with the elimination inside
   // the preconditioner).

@@ -58,7 +58,7 @@ def test_single_level_is_exact_pinv(ctx):
 def test_block_widths_weighted_random(ctx, W):
     eg = synth.random_connected(1500, 6000, seed=W)
     say("widths", W, eg.n, eg.m)
-    g = load(ctx, eg, coarsest_max=64)
+    g = load(ctx, eg, coarsest_max=64, max_complexity=-1)
     assert g.info()["levels"] >= 3
     _, Rm = dense_R(eg)
     rng = np.random.default_rng(W)
@@ -96,7 +96,7 @@ def hub_graph(seed=21):
 def test_heavy_rows(ctx, W, depth):
     eg = hub_graph()
     say("heavy rows", W, depth, eg.n, eg.m)
-    g = load(ctx, eg, coarsest_max=64)
+    g = load(ctx, eg, coarsest_max=64, max_complexity=-1)
     Lp, Rm = dense_R(eg)
     rng = np.random.default_rng(W)
     s = rng.integers(0, eg.n, W + 5)
@@ -110,6 +110,28 @@ def test_heavy_rows(ctx, W, depth):
     far, _ = g.farness_jl(nodes)
     of, _, _ = E.projection(None, eg, nodes, 40, 3, solver="dense", Lp=Lp)
     np.testing.assert_allclose(far, of, rtol=1e-6)
+
+
+def test_budget_truncated_hierarchy(ctx):
+    """Under the default complexity budget a Barabasi-Albert graph keeps one
+    aggregation level of more than 4096 nodes and no exact coarsest solve:
+    the full-depth cycle ends there with a Jacobi step, and every depth still
+    gives the oracle's resistances."""
+    eg = synth.barabasi_albert(15000, 4, seed=12)
+    g = load(ctx, eg, coarsest_max=64)
+    info = g.info()
+    say("budget", info["levels"], info["level_n"], info["operator_complexity"])
+    assert info["operator_complexity"] <= 2.0 and info["level_n"][-1] > 4096
+    assert g.level(info["levels"] - 1)["coarse_pinv"] is None
+    rng = np.random.default_rng(5)
+    s = rng.integers(0, eg.n, 70)
+    t = rng.integers(0, eg.n, 70)
+    want = R.resistance_cg(LAP.of(eg), s, t, tol=1e-12)
+    for depth in (1, 2, 0):
+        for prec, tol, rt in [(0, 1e-8, 1e-7), (1, 1e-10, 1e-9)]:
+            r, st = g.resistance(s, t, block=64, precision=prec, tol=tol, levels=depth, stats=True)
+            say("  depth", depth, prec, st["levels_used"], st["inner_iters"])
+            np.testing.assert_allclose(r, want, rtol=rt, atol=1e-12)
 
 
 @pytest.mark.parametrize("depth", [1, 2, 3, 0])
@@ -325,7 +347,7 @@ def test_elimination_level_all_depths(ctx, W, prec):
     and the full exact path give the oracle's resistances."""
     eg = leafy_graph(seed=W)
     say("elimination", W, prec, eg.n, eg.m)
-    g = load(ctx, eg, coarsest_max=64, eliminate=2)
+    g = load(ctx, eg, coarsest_max=64, eliminate=2, max_complexity=-1)
     info = g.info()
     assert info["eliminated"] > eg.n // 10 and info["levels"] >= 4
     _, Rm = dense_R(eg)
@@ -351,7 +373,7 @@ def test_schur_cg_matches_level0_cg(ctx, W, monkeypatch):
     iterations, also on an R-MAT graph whose hubs are heavy rows of the
     Schur complement, and with the iterations replayed from a HIP graph."""
     for name, eg in [("leafy", leafy_graph(seed=W + 1)), ("rmat", synth.rmat(11, seed=W))]:
-        g = load(ctx, eg, coarsest_max=64, eliminate=2)
+        g = load(ctx, eg, coarsest_max=64, eliminate=2, max_complexity=-1)
         assert g.info()["eliminated"] > 0
         _, Rm = dense_R(eg)
         rng = np.random.default_rng(W)
@@ -380,7 +402,7 @@ def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
         depth, W = 1, 256
     else:
         eg = leafy_graph(seed=45)
-        g = load(ctx, eg, coarsest_max=64, eliminate=2)
+        g = load(ctx, eg, coarsest_max=64, eliminate=2, max_complexity=-1)
         assert g.info()["eliminated"] > 0 and g.info()["levels"] >= 3
         depth, W = 2, 64
     _, Rm = dense_R(eg)

@@ -129,7 +129,7 @@ def l_ok(nc, n):
 def test_hierarchy_invariants(hctx, maker, elim):
     eg = maker()
     g = cfc.Graph.from_edgelist(hctx, eg)
-    g.build_hierarchy(coarsest_max=128, eliminate=elim)
+    g.build_hierarchy(coarsest_max=128, eliminate=elim, max_complexity=-1)  # every level
     info = g.info()
     L = info["levels"]
     assert L >= 2 and info["level_n"][-1] <= 128
@@ -167,6 +167,28 @@ def test_hierarchy_invariants(hctx, maker, elim):
     np.testing.assert_allclose(Lc @ Pc @ Lc, Lc, atol=1e-8 * np.abs(Lc).max())
     np.testing.assert_allclose(Pc.sum(axis=1), 0, atol=1e-9)
     np.testing.assert_allclose(Pc, R.pinv(Lc), atol=1e-8 * max(1.0, np.abs(Pc).max()))
+
+
+def test_complexity_budget(hctx):
+    """The default budget keeps sum_l (nnz_l + n_l) / (nnz_0 + n_0) <= 2: on a
+    Barabasi-Albert graph the quotient graphs keep almost every edge, so it
+    stops after one aggregation level, above 4096 nodes here and so with no
+    exact coarsest solve; a road grid coarsens as far as without a budget."""
+    ba = synth.barabasi_albert(20000, 4, seed=3)
+    full = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, max_complexity=-1).info()
+    assert full["operator_complexity"] > 2.0
+    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128)
+    info = g.info()
+    assert info["operator_complexity"] <= 2.0 and 2 <= info["levels"] < full["levels"]
+    assert info["level_n"][-1] > 4096 and g.level(info["levels"] - 1)["coarse_pinv"] is None
+    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, max_complexity=3.0)
+    assert g.info()["operator_complexity"] <= 3.0
+    rd = synth.road_grid(100, seed=2)
+    a = cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(coarsest_max=64).info()
+    b = cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(coarsest_max=64, max_complexity=-1).info()
+    assert a["levels"] == b["levels"] and a["operator_complexity"] <= 2.0
+    with pytest.raises(cfc.CfcError, match="INVALID"):
+        cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(max_complexity=0.5)
 
 
 def test_tiny_graph_single_level(hctx):

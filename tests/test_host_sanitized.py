@@ -21,8 +21,18 @@ def asan_runtime():
     return path if r.returncode == 0 and os.path.isfile(path) else None
 
 
-def test_host_suite_under_asan_and_ubsan():
+def stale():
+    """The sanitized build is missing or older than a source or header."""
     if not os.path.exists(SAN_LIB):
+        return True
+    t = os.path.getmtime(SAN_LIB)
+    srcs = [os.path.join(d, f) for d in (os.path.join(ROOT, "paper_1607_02955_amd", "csrc"),
+                                          os.path.join(ROOT, "include")) for f in os.listdir(d)]
+    return any(os.path.getmtime(f) > t for f in srcs)
+
+
+def test_host_suite_under_asan_and_ubsan():
+    if stale():
         sys.path.insert(0, ROOT)
         from paper_1607_02955_amd import build as B
         B.build(verbose=False, sanitize=True)
