@@ -576,18 +576,22 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
            w.scal.as<double>(), stream, w.mirror_dev);
 }
 
-void Solver::capture_pair() {
+void Solver::capture_iterations() {
   Workspace& w = *ws;
   const double b0 = bytes;
   const bool prof = profile;
-  profile = false;  // no event records inside the captured graph
-  CFC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  iteration(false, w.rb.p, w.ra.p);
-  iteration(false, w.ra.p, w.rb.p);
-  CFC_HIP(hipStreamEndCapture(stream, &graph));
+  profile = false;  // no event records inside the captured graphs
+  for (int k = 0; k < 2; ++k) {
+    CFC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    if (k == 0)
+      iteration(false, w.rb.p, w.ra.p);
+    else
+      iteration(false, w.ra.p, w.rb.p);
+    CFC_HIP(hipStreamEndCapture(stream, &graph[k]));
+    CFC_HIP(hipGraphInstantiate(&gexec[k], graph[k], nullptr, nullptr, 0));
+  }
   profile = prof;
-  CFC_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-  pair_bytes = bytes - b0;
+  iter_bytes = (bytes - b0) / 2;
   bytes = b0;
 }
 
@@ -680,13 +684,14 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
   iteration(true, r0, w.rb.p);
   if (max_inner == 1 || (first_check <= 1 && 1 % check_every == 0 && converged())) return record(it);
   if (params.use_graph) {
-    if (!gexec) capture_pair();
+    // the residual is in r_b after odd iterations, in r_a after even ones
+    if (!gexec[0]) capture_iterations();
     while (it < max_inner) {
-      CFC_HIP(hipGraphLaunch(gexec, stream));
-      it += 2;
-      bytes += pair_bytes;
+      CFC_HIP(hipGraphLaunch(gexec[it % 2 == 1 ? 0 : 1], stream));
+      ++it;
+      bytes += iter_bytes;
       graph_replays++;
-      if (it + 1 >= first_check && (it / 2) % std::max(1, check_every / 2) == 0 && converged()) break;
+      if (it >= first_check && (it % check_every == 0 || it == max_inner) && converged()) break;
     }
     return record(it);
   }
@@ -837,8 +842,10 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
 }
 
 Solver::~Solver() {
-  if (gexec) (void)hipGraphExecDestroy(gexec);
-  if (graph) (void)hipGraphDestroy(graph);
+  for (int k = 0; k < 2; ++k) {
+    if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+    if (graph[k]) (void)hipGraphDestroy(graph[k]);
+  }
   for (auto& e : prof_ev) {
     (void)hipEventDestroy(e.a);
     if (e.b) (void)hipEventDestroy(e.b);

@@ -92,14 +92,14 @@ struct Solver {
   Solver(Graph& g, const cfc_solve_params& p, hipStream_t stream_override = nullptr,
          Ctx* mem = nullptr);
   ~Solver();
-  // HIP graph of two PCG iterations (r_b -> r_a, then r_a -> r_b), built on
-  // first use and replayed between host convergence checks
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // HIP graphs of one PCG iteration each, r_b -> r_a ([0]) and r_a -> r_b
+  // ([1]), built on first use and replayed alternately
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int64_t graph_replays = 0;
-  double pair_bytes = 0;
+  double iter_bytes = 0;
   void iteration(bool first, void* r_in, void* r_out);
-  void capture_pair();
+  void capture_iterations();
   void vcycle(bool update, bool first_x, const void* r_in, void* r_out);
   void vcycle_elim(bool update, bool first_x, const void* r_in, void* r_out);
   int pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
