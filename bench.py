@@ -303,9 +303,11 @@ def cpu_baseline(eg, spec, nodes, budget_s=20.0):
 
 
 def setup_times(args):
-    """Hierarchy setup (host C++ build vs the device build) on the BA-100k,
-    R-MAT-20 and road-2048^2 graphs; each build is timed after a warm-up
-    build of the same graph."""
+    """Hierarchy setup on the BA-100k, R-MAT-20 and road-2048^2 graphs: the
+    host C++ build, the device build (device = 1: affinities, Galerkin
+    products and renumbering on the GPU, bit-identical to the host build)
+    and the device build with the aggregation on the GPU too (device = 2);
+    each build is timed after a warm-up build of the same graph."""
     import torch
 
     import paper_1607_02955_amd as cfc
@@ -317,21 +319,25 @@ def setup_times(args):
                         ("road2048", synth.road_grid, (2048,))]:
         eg = synth.cached(name, fn, *a, seed=1)
         print(f"# {name}: n={eg.n} m={eg.m}", file=sys.stderr, flush=True)
-        t = {}
-        for dev in (1, 0, 1):
+        t, lev = {}, {}
+        names = {0: "host", 1: "device", 2: "device_agg"}
+        for dev in (1, 0, 1, 2, 2):
             g = cfc.Graph.from_edgelist(ctx, eg)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             g.build_hierarchy(device=dev)
             torch.cuda.synchronize()
-            t["device" if dev else "host"] = time.perf_counter() - t0
+            t[names[dev]] = time.perf_counter() - t0
             info = g.info()
-            print(f"#   {'device' if dev else 'host'} build {t['device' if dev else 'host']:.2f} s",
-                  file=sys.stderr, flush=True)
+            lev[names[dev]] = (info["levels"], round(info["operator_complexity"], 3))
+            print(f"#   {names[dev]} build {t[names[dev]]:.2f} s", file=sys.stderr, flush=True)
             del g
-        rows.append({"graph": name, "n": eg.n, "m": eg.m, "levels": info["levels"],
-                     "eliminated": info["eliminated"], "host_s": round(t["host"], 3),
-                     "device_s": round(t["device"], 3), "speedup": round(t["host"] / t["device"], 2)})
+        rows.append({"graph": name, "n": eg.n, "m": eg.m, "levels": lev["device"][0],
+                     "operator_complexity": lev["device"][1], "eliminated": info["eliminated"],
+                     "host_s": round(t["host"], 3), "device_s": round(t["device"], 3),
+                     "speedup": round(t["host"] / t["device"], 2),
+                     "device_agg_s": round(t["device_agg"], 3), "device_agg_levels": lev["device_agg"][0],
+                     "device_agg_operator_complexity": lev["device_agg"][1]})
     out = {"metric": "hierarchy setup seconds (device build)", "value": rows[1]["device_s"], "unit": "s",
            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * rows[1]["device_s"], 1),
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

@@ -123,9 +123,15 @@ typedef struct {
                             any node qualifies */
   int32_t device;        /* 1 = run the affinity, Galerkin and renumbering
                             steps on the context's GPU (default; the result
-                            is bit-identical to the host build), 0 = host
-                            only.  Host-only contexts always build on the
-                            host. */
+                            is bit-identical to the host build); 2 = the
+                            aggregation too (Sec. 3.1's aggregation by
+                            affinity, done by parallel handshake matching:
+                            every unassigned node picks its strongest
+                            unassigned neighbour, mutual picks pair up,
+                            leftovers join their strongest neighbour's
+                            aggregate; deterministic, but other aggregates
+                            than the host's greedy pass); 0 = host only.
+                            Host-only contexts always build on the host. */
   int32_t order;         /* locality keys of the nested renumbering:
                             1 = Cuthill-McKee sweep, 2 = input node order,
                             3 = descending degree (hubs first, which keeps

@@ -406,7 +406,7 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device);
 }
 
 void build_hierarchy(Graph& g, const cfc_setup_params& p) {
-  const bool on_device = p.device == 1 && !g.ctx->host_only();
+  const bool on_device = p.device >= 1 && !g.ctx->host_only();
   try {
     build_hierarchy_impl(g, p, on_device);
   } catch (const Error& e) {
@@ -440,7 +440,7 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
     BLevel R;
     if (B[0].n > p.coarsest_max && eliminate(B[0], p.eliminate, R)) B.push_back(std::move(R));
   }
-  if (p.device != 0 && p.device != 1) fail(CFC_E_INVALID, "device must be 0 or 1");
+  if (p.device < 0 || p.device > 2) fail(CFC_E_INVALID, "device must be 0, 1 or 2");
   if (p.order < 0 || p.order > 3) fail(CFC_E_INVALID, "order must be 0, 1, 2 or 3");
   std::unique_ptr<DeviceSetup> dev;
   std::vector<int> dh;  // device handle of each build level
@@ -470,8 +470,14 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
     std::vector<int32_t> agg;
     auto ta = std::chrono::steady_clock::now();
     const int lvl = (int)B.size() - 1;
-    const std::vector<double> aff = dev ? dev->affinities(dh[lvl], lvl, p) : affinities(F, lvl, p);
-    int64_t nc = aggregate(F, aff, p, agg);
+    int64_t nc;
+    if (dev && p.device == 2) {  // aggregation on the device too
+      dev->affinities(dh[lvl], lvl, p, true);
+      nc = dev->aggregate(dh[lvl], std::max(2, p.agg_cap), agg);
+    } else {
+      const std::vector<double> aff = dev ? dev->affinities(dh[lvl], lvl, p) : affinities(F, lvl, p);
+      nc = aggregate(F, aff, p, agg);
+    }
     const double t_agg = ms_since(ta);
     if (nc >= F.n) break;  // no progress (cannot happen on a connected graph with n >= 2)
     ta = std::chrono::steady_clock::now();

@@ -35,7 +35,14 @@ class DeviceSetup {
   ~DeviceSetup();
   // upload a level's CSR; returns its handle
   int add(const BLevel& L);
-  std::vector<double> affinities(int lv, int level, const cfc_setup_params& p);
+  // keep = true: leave them on the device for aggregate() (nothing returned)
+  std::vector<double> affinities(int lv, int level, const cfc_setup_params& p, bool keep = false);
+  // parallel aggregation of level lv over its kept affinities: handshake
+  // matching rounds, every unmatched node joining its strongest matched
+  // neighbour's aggregate, then two rounds of handshake matching between
+  // aggregates (merged size at most cap); agg (host) numbers the aggregates
+  // in the order of their roots.  Returns their number.
+  int64_t aggregate(int lv, int cap, std::vector<int32_t>& agg);
   // quotient graph of level lv under agg (host array), downloaded into C and
   // kept on the device; returns its handle
   int galerkin(int lv, const std::vector<int32_t>& agg, int64_t nc, BLevel& C);

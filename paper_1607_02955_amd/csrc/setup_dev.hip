@@ -1,9 +1,11 @@
 // Device side of the hierarchy setup: test-vector relaxation and edge
 // affinities, Galerkin quotient graphs (P^T L P for piecewise-constant P)
-// and the final renumbering of every level's CSR.  The greedy aggregation,
-// the elimination choice and the Cuthill-McKee keys stay on the host.
+// and the final renumbering of every level's CSR; with device = 2 also the
+// aggregation itself (parallel handshake matching).  The elimination choice
+// and the locality keys stay on the host.
 //
-// Every result equals the host build bit for bit: the kernels perform the
+// With device = 1 every result equals the host build bit for bit (the
+// parallel aggregation of device = 2 forms other aggregates): the kernels perform the
 // host's FP64 operations in the host's order with contraction switched off,
 // sums over a coarse edge run over the fine edges in CSR order (a stable
 // radix sort keeps that order inside each key), and a coarse row's degree
@@ -108,6 +110,130 @@ __global__ void k_affinity(int64_t nnz, int K, const int32_t* __restrict__ erow,
   aff[e] = a * (1.0 + 1e-12 * w[e]);
 }
 
+// ---- parallel aggregation (device = 2) --------------------------------------
+// Handshake matching on the affinities: every unassigned node picks its
+// strongest unassigned neighbour (ties to the lower id); two nodes that pick
+// each other form an aggregate labelled by the lower id.  After a few rounds
+// every node still unassigned joins the aggregate of its strongest assigned
+// neighbour, and a node with none founds its own.  All steps read labels of
+// the previous step only, so the result does not depend on thread order.
+
+__global__ void k_agg_pick(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                           const double* __restrict__ aff, const int32_t* __restrict__ agg,
+                           int32_t* __restrict__ pick) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int32_t best = -1;
+  double ba = -1.0;
+  if (agg[u] < 0)
+    for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      const int32_t v = col[e];
+      if (agg[v] >= 0) continue;
+      const double a = aff[e];
+      if (a > ba || (a == ba && v < best)) {
+        ba = a;
+        best = v;
+      }
+    }
+  pick[u] = best;
+}
+
+__global__ void k_agg_match(int64_t n, const int32_t* __restrict__ pick, int32_t* __restrict__ agg,
+                            int32_t* __restrict__ matched) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int32_t v = pick[u];
+  if (v > u && pick[v] == (int32_t)u) {  // mutual: the lower id writes both labels
+    agg[u] = (int32_t)u;
+    agg[v] = (int32_t)u;
+    matched[0] = 1;
+  }
+}
+
+// unassigned u -> label of its strongest assigned neighbour (or its own id
+// when found = 1 and it has none); assigned nodes keep theirs
+__global__ void k_agg_attach(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                             const double* __restrict__ aff, const int32_t* __restrict__ agg,
+                             int32_t* __restrict__ out, int found) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int32_t lab = agg[u];
+  if (lab < 0) {
+    int32_t best = -1;
+    double ba = -1.0;
+    for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      const int32_t v = col[e];
+      if (agg[v] < 0) continue;
+      const double a = aff[e];
+      if (a > ba || (a == ba && v < best)) {
+        ba = a;
+        best = v;
+      }
+    }
+    lab = best >= 0 ? agg[best] : (found ? (int32_t)u : -1);
+  }
+  out[u] = lab;
+}
+
+// Matching between aggregates (labels are root ids): every edge between two
+// aggregates offers its affinity to the aggregate of its row; each aggregate
+// keeps the largest offer from an aggregate it may merge with (the merged
+// size within cap), ties to the lower label.  The offer is packed as
+// (float bits of the affinity, ~label) so one 64-bit atomicMax keeps it; the
+// maximum does not depend on the order of the atomics.
+__global__ void k_agg_size(int64_t n, const int32_t* __restrict__ lab, int32_t* __restrict__ size) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) atomicAdd(&size[lab[u]], 1);
+}
+
+__global__ void k_agg_offer(int64_t nnz, const int32_t* __restrict__ erow, const int32_t* __restrict__ col,
+                            const double* __restrict__ aff, const int32_t* __restrict__ lab,
+                            const int32_t* __restrict__ size, int cap,
+                            unsigned long long* __restrict__ best) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int32_t A = lab[erow[e]], B = lab[col[e]];
+  if (A == B || size[A] + size[B] > cap) return;
+  const float a = (float)aff[e];  // affinities are >= 0, so the bits order like the values
+  const unsigned long long key = ((unsigned long long)__float_as_uint(a) << 32) | (0xFFFFFFFFull - (uint32_t)B);
+  atomicMax(&best[A], key);
+}
+
+__global__ void k_agg_merge(int64_t n, const int32_t* __restrict__ lab, const unsigned long long* __restrict__ best,
+                            int32_t* __restrict__ into, int32_t* __restrict__ merged) {
+  const int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= n || lab[A] != (int32_t)A || best[A] == 0) return;
+  const int32_t B = (int32_t)(0xFFFFFFFFull - (best[A] & 0xFFFFFFFFull));
+  if (B <= A || best[B] == 0) return;
+  const int32_t back = (int32_t)(0xFFFFFFFFull - (best[B] & 0xFFFFFFFFull));
+  if (back == (int32_t)A) {  // mutual: B's members take label A
+    into[B] = (int32_t)A;
+    merged[0] = 1;
+  }
+}
+
+__global__ void k_agg_iota(int64_t n, int32_t* __restrict__ x) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) x[u] = (int32_t)u;
+}
+
+__global__ void k_agg_relabel(int64_t n, const int32_t* __restrict__ lab, const int32_t* __restrict__ into,
+                              int32_t* __restrict__ out) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) out[u] = into[lab[u]];
+}
+
+__global__ void k_agg_roots(int64_t n, const int32_t* __restrict__ agg, int32_t* __restrict__ root) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) root[u] = agg[u] == (int32_t)u ? 1 : 0;
+}
+
+__global__ void k_agg_compact(int64_t n, const int32_t* __restrict__ agg, const int32_t* __restrict__ id,
+                              int32_t* __restrict__ out) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) out[u] = id[agg[u]];
+}
+
 constexpr uint64_t kNoKey = ~0ull;
 
 // coarse key (I, J) of every fine entry; entries inside an aggregate sort last
@@ -206,6 +332,8 @@ struct DeviceSetup::Impl {
   hipStream_t s;
   std::vector<std::unique_ptr<DevCSR>> lv;
   DBuf tmp;  // radix-sort / scan scratch
+  DBuf aff;  // affinities kept for the device aggregation of level aff_lv
+  int aff_lv = -1;
 
   void* scratch(size_t bytes) {
     if (tmp.bytes < bytes) tmp.alloc(ctx, bytes);
@@ -245,7 +373,7 @@ int DeviceSetup::add(const BLevel& L) {
   return (int)d->lv.size() - 1;
 }
 
-std::vector<double> DeviceSetup::affinities(int lv, int level, const cfc_setup_params& p) {
+std::vector<double> DeviceSetup::affinities(int lv, int level, const cfc_setup_params& p, bool keep) {
   const DevCSR& c = *d->lv[lv];
   const int64_t n = c.n;
   const int K = std::max(1, p.test_vectors);
@@ -274,8 +402,105 @@ std::vector<double> DeviceSetup::affinities(int lv, int level, const cfc_setup_p
     hipLaunchKernelGGL(k_affinity, dim3(blocks_for(c.nnz)), dim3(kT), 0, s, c.nnz, K,
                        c.erow.as<int32_t>(), c.col.as<int32_t>(), c.w.as<double>(), X.as<double>(),
                        nx.as<double>(), aff.as<double>());
+  if (keep) {
+    d->aff = std::move(aff);
+    d->aff_lv = lv;
+    return out;
+  }
   get(out, aff, c.nnz, s);
   return out;
+}
+
+int64_t DeviceSetup::aggregate(int lv, int cap, std::vector<int32_t>& agg) {
+  const DevCSR& c = *d->lv[lv];
+  if (d->aff_lv != lv) fail(CFC_E_INTERNAL, "device affinities are not those of this level");
+  const int64_t n = c.n;
+  hipStream_t s = d->s;
+  agg.assign(n, 0);
+  if (n == 0) return 0;
+  DBuf a0, a1, pick, flag, root, id;
+  a0.alloc(d->ctx, n * 4);
+  a1.alloc(d->ctx, n * 4);
+  pick.alloc(d->ctx, n * 4);
+  flag.alloc(d->ctx, 4);
+  root.alloc(d->ctx, n * 4);
+  id.alloc(d->ctx, n * 4);
+  std::vector<int32_t> init(n, -1);
+  CFC_HIP(hipMemcpyAsync(a0.p, init.data(), n * 4, hipMemcpyHostToDevice, s));
+  const int32_t* rp = c.rowptr.as<int32_t>();
+  const int32_t* cl = c.col.as<int32_t>();
+  const double* af = d->aff.as<double>();
+  // Matching rounds until one pairs nobody: the affinities are symmetric and
+  // ties go to the lower id, so while an edge joins two unassigned nodes the
+  // strongest such edge is a mutual pick, and a round without a match means
+  // every unassigned node has only assigned neighbours (or none).  Then the
+  // unassigned join an assigned neighbour (or found their own aggregate).
+  // A round cap bounds the work; a capped pass attaches what it can and
+  // starts again.
+  for (int outer = 0; outer < 64; ++outer) {
+    int32_t m = 1;
+    for (int r = 0; r < 32 && m; ++r) {
+      int32_t zero = 0;
+      CFC_HIP(hipMemcpyAsync(flag.p, &zero, 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_agg_pick, dim3(blocks_for(n)), dim3(kT), 0, s, n, rp, cl, af, a0.as<int32_t>(),
+                         pick.as<int32_t>());
+      hipLaunchKernelGGL(k_agg_match, dim3(blocks_for(n)), dim3(kT), 0, s, n, pick.as<int32_t>(),
+                         a0.as<int32_t>(), flag.as<int32_t>());
+      CFC_HIP(hipMemcpyAsync(&m, flag.p, 4, hipMemcpyDeviceToHost, s));
+      CFC_HIP(hipStreamSynchronize(s));
+    }
+    const int found = (m == 0 || outer == 63) ? 1 : 0;
+    hipLaunchKernelGGL(k_agg_attach, dim3(blocks_for(n)), dim3(kT), 0, s, n, rp, cl, af, a0.as<int32_t>(),
+                       a1.as<int32_t>(), found);
+    std::swap(a0.p, a1.p);
+    get(agg, a0, n, s);
+    bool done = true;
+    for (int64_t u = 0; u < n && done; ++u) done = agg[u] >= 0;
+    if (done) break;
+  }
+  for (int64_t u = 0; u < n; ++u)
+    if (agg[u] < 0) fail(CFC_E_INTERNAL, "device aggregation left a node unplaced");
+  // Two rounds of matching between aggregates (pairs of pairs), each merge
+  // within agg_cap nodes: coarsening by about four per level, as the host's
+  // greedy pass does (pairs alone coarsen by ~2.2, which the complexity
+  // budget cuts off long before the coarsest level on road grids).
+  {
+    DBuf size, best, into;
+    size.alloc(d->ctx, n * 4);
+    best.alloc(d->ctx, n * 8);
+    into.alloc(d->ctx, n * 4);
+    for (int r = 0; r < 2; ++r) {
+      CFC_HIP(hipMemsetAsync(size.p, 0, n * 4, s));
+      CFC_HIP(hipMemsetAsync(best.p, 0, n * 8, s));
+      int32_t zero = 0, m = 0;
+      CFC_HIP(hipMemcpyAsync(flag.p, &zero, 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_agg_size, dim3(blocks_for(n)), dim3(kT), 0, s, n, a0.as<int32_t>(), size.as<int32_t>());
+      if (c.nnz)
+        hipLaunchKernelGGL(k_agg_offer, dim3(blocks_for(c.nnz)), dim3(kT), 0, s, c.nnz, c.erow.as<int32_t>(), cl,
+                           af, a0.as<int32_t>(), size.as<int32_t>(), cap, best.as<unsigned long long>());
+      hipLaunchKernelGGL(k_agg_iota, dim3(blocks_for(n)), dim3(kT), 0, s, n, into.as<int32_t>());
+      hipLaunchKernelGGL(k_agg_merge, dim3(blocks_for(n)), dim3(kT), 0, s, n, a0.as<int32_t>(),
+                         best.as<unsigned long long>(), into.as<int32_t>(), flag.as<int32_t>());
+      hipLaunchKernelGGL(k_agg_relabel, dim3(blocks_for(n)), dim3(kT), 0, s, n, a0.as<int32_t>(),
+                         into.as<int32_t>(), a1.as<int32_t>());
+      std::swap(a0.p, a1.p);
+      CFC_HIP(hipMemcpyAsync(&m, flag.p, 4, hipMemcpyDeviceToHost, s));
+      CFC_HIP(hipStreamSynchronize(s));
+      if (!m) break;
+    }
+  }
+  // aggregates numbered in order of their root (the lower id of the pair)
+  hipLaunchKernelGGL(k_agg_roots, dim3(blocks_for(n)), dim3(kT), 0, s, n, a0.as<int32_t>(), root.as<int32_t>());
+  size_t bytes = 0;
+  CFC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, root.as<int32_t>(), id.as<int32_t>(), n, s));
+  void* t = d->scratch(bytes);
+  CFC_HIP(hipcub::DeviceScan::ExclusiveSum(t, bytes, root.as<int32_t>(), id.as<int32_t>(), n, s));
+  hipLaunchKernelGGL(k_agg_compact, dim3(blocks_for(n)), dim3(kT), 0, s, n, a0.as<int32_t>(), id.as<int32_t>(),
+                     a1.as<int32_t>());
+  get(agg, a1, n, s);
+  int64_t nc = 0;
+  for (int64_t u = 0; u < n; ++u) nc = std::max<int64_t>(nc, (int64_t)agg[u] + 1);
+  return nc;
 }
 
 int DeviceSetup::galerkin(int lv, const std::vector<int32_t>& agg, int64_t nc, BLevel& C) {

@@ -112,6 +112,51 @@ def test_heavy_rows(ctx, W, depth):
     np.testing.assert_allclose(far, of, rtol=1e-6)
 
 
+@pytest.mark.parametrize("maker", [
+    lambda: synth.grid(40),
+    lambda: synth.road_grid(60, seed=8),
+    lambda: synth.barabasi_albert(3000, 4, seed=2),
+    lambda: synth.rmat(11, seed=3),
+    lambda: synth.star_graph(1500),
+    lambda: leafy_graph(seed=9),
+])
+def test_device_aggregation(ctx, maker):
+    """device = 2: the aggregation pass runs on the GPU (handshake matching).
+    Every aggregation level is a partition into contiguous row ranges, the
+    next level is P^T L P with zero row sums, the build is deterministic, and
+    the full-depth cycle gives the oracle's resistances."""
+    from tests.test_host import _check_elimination_level, _level_laplacian
+    eg = maker()
+    say("device aggregation", eg.n, eg.m)
+    g = load(ctx, eg, coarsest_max=64, device=2, max_complexity=-1, eliminate=2)
+    info = g.info()
+    L = info["levels"]
+    assert L >= 2 and info["level_n"][-1] <= 64
+    for l in range(L - 1):
+        lv, nxt = g.level(l), g.level(l + 1)
+        if lv["elimination"]:
+            _check_elimination_level(lv, nxt)
+            continue
+        agg, ap = lv["agg"], lv["agg_ptr"]
+        assert ap[0] == 0 and ap[-1] == lv["n"] and np.all(np.diff(ap) >= 1)
+        assert np.all(np.diff(agg) >= 0)
+        Lf = _level_laplacian(lv)
+        P = np.zeros((lv["n"], lv["n_coarse"]))
+        P[np.arange(lv["n"]), agg] = 1.0
+        Lc = _level_laplacian(nxt)
+        np.testing.assert_allclose(P.T @ Lf @ P, Lc, atol=1e-9 * max(1.0, np.abs(Lc).max()))
+        np.testing.assert_allclose(Lc.sum(axis=1), 0, atol=1e-9 * max(1.0, np.abs(Lc).max()))
+    g2 = load(ctx, eg, coarsest_max=64, device=2, max_complexity=-1, eliminate=2)
+    assert g2.info()["level_n"] == info["level_n"] and g2.info()["level_nnz"] == info["level_nnz"]
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(7)
+    s = rng.integers(0, eg.n, 70)
+    t = rng.integers(0, eg.n, 70)
+    r, st = g.resistance(s, t, block=64, tol=1e-9, levels=0, stats=True, max_inner=3000)
+    say("  levels", info["level_n"], "iters", st["inner_iters"])
+    np.testing.assert_allclose(r, Rm[s, t], rtol=1e-8, atol=1e-12)
+
+
 def test_budget_truncated_hierarchy(ctx):
     """Under the default complexity budget a Barabasi-Albert graph keeps one
     aggregation level of more than 4096 nodes and no exact coarsest solve:
