@@ -273,6 +273,6 @@ def test_locality_orders_give_valid_nested_hierarchies(hctx, order):
 def test_setup_param_errors_enums(hctx):
     eg = synth.path_graph(10)
     g = cfc.Graph.from_edgelist(hctx, eg)
-    for kw in ({"order": 4}, {"eliminate": 3}, {"device": 2}):
+    for kw in ({"order": 4}, {"eliminate": 3}, {"device": 3}):
         with pytest.raises(cfc.CfcError):
             g.build_hierarchy(**kw)
