@@ -361,6 +361,10 @@ def main():
                     help="locality order of the hierarchy: 0 auto, 1 Cuthill-McKee, 2 input, 3 hubs first")
     ap.add_argument("--eliminate", type=int, default=1,
                     help="low-degree elimination level: 0 off, 1 when >= 5%% of nodes qualify, 2 always")
+    ap.add_argument("--elim-degree", type=int, default=0,
+                    help="largest degree of an eliminated node (0 = the library default)")
+    ap.add_argument("--nest", type=int, default=0,
+                    help="aggregation levels the numbering nests (0 = auto, 1 = all, 2 = kept)")
     ap.add_argument("--block", type=int, default=-1, help="block width W (default: the workload's)")
     ap.add_argument("--use-graph", type=int, default=-1,
                     help="replay PCG iterations from HIP graphs (1/0; default: on)")
@@ -467,7 +471,8 @@ def measure(workload, args, extras=True, ctx=None):
     ctx = ctx or cfc.Context(0)
     g = cfc.Graph.from_edgelist(ctx, eg)
     t0 = time.perf_counter()
-    g.build_hierarchy(eliminate=args.eliminate, order=args.order)
+    g.build_hierarchy(eliminate=args.eliminate, order=args.order, elim_degree=args.elim_degree,
+                      nest=args.nest)
     setup_s = time.perf_counter() - t0
     info = g.info()
     progress(f"hierarchy: {info['levels']} levels, {info['eliminated']} eliminated, {setup_s:.1f} s")
@@ -574,8 +579,13 @@ def measure(workload, args, extras=True, ctx=None):
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(workload, kname),
                 "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": per_launch, "launches": agg["kl"][dom],
-                "share_of_solve_time": round(agg["kms"][dom] / max(agg["solve_ms"], 1e-9), 3)}
+                "algorithmic_bytes_per_launch": per_launch, "launches_timed": agg["kl"][dom],
+                # each PCG iteration launches each level-0 kernel kind once;
+                # launches replayed from HIP graphs carry no events, so the
+                # share counts them at the timed launches' average duration
+                "launches": max(agg["iters"], agg["kl"][dom]),
+                "share_of_solve_time": round(avg_ms * max(agg["iters"], agg["kl"][dom]) /
+                                             max(agg["solve_ms"], 1e-9), 3)}
         hd = int(os.environ.get("CFC_HEAVY_DEG", "256"))
         deg = np.bincount(eg.u, minlength=eg.n) + np.bincount(eg.v, minlength=eg.n)
         nheavy = int((deg > hd).sum())
@@ -593,7 +603,8 @@ def measure(workload, args, extras=True, ctx=None):
                    "vcycle_depth": agg.get("depth"), "hip_graph": bool(use_graph),
                    "tol": spec["tol"], "query_nodes": spec["queries"], "levels": info["levels"],
                    "eliminated_nodes": info["eliminated"],
-                   "operator_complexity": round(info["operator_complexity"], 3)},
+                   "operator_complexity": round(info["operator_complexity"], 3),
+                   "cycle_complexity": round(info["cycle_complexity"], 3)},
         "roofline": roof,
         "solve": {"pcg_iters_per_step": agg["iters"] / args.steps,
                   "refine_steps_per_step": agg["refine"] / args.steps,

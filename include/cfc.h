@@ -69,6 +69,7 @@ extern "C" {
 #define CFC_PREC_FP64          1  /* FP64 multigrid-PCG throughout */
 
 #define CFC_MAX_LEVELS        32
+#define CFC_ELIM_MAX_DEGREE    4  /* eliminated nodes have at most this degree */
 
 typedef struct cfc_ctx cfc_ctx;
 typedef struct cfc_graph cfc_graph;
@@ -104,6 +105,10 @@ typedef struct {
   int32_t max_degree;
   int32_t eliminated;              /* nodes removed by the elimination level
                                       (0 = none) */
+  double cycle_complexity;         /* the same sum from the first aggregated
+                                      level a on, over level a's nnz+n (a = 1
+                                      behind an elimination level: the inner
+                                      solve iterates on its Schur complement) */
 } cfc_graph_info;
 
 typedef struct {
@@ -116,11 +121,11 @@ typedef struct {
   uint64_t seed;         /* test-vector seed (1) */
   int32_t eliminate;     /* low-degree elimination level (Sec. 3.1: LAMG
                             alternates elimination and aggregation): an
-                            independent set of degree-1 and degree-2 nodes
-                            is removed exactly by a Schur complement before
-                            aggregating.  0 = off, 1 = when it removes at
-                            least 5% of the nodes (default), 2 = whenever
-                            any node qualifies */
+                            independent set of nodes of degree at most
+                            elim_degree is removed exactly by a Schur
+                            complement before aggregating.  0 = off, 1 =
+                            when it removes at least 5% of the nodes
+                            (default), 2 = whenever any node qualifies */
   int32_t device;        /* 1 = run the affinity, Galerkin and renumbering
                             steps on the context's GPU (default; the result
                             is bit-identical to the host build); 2 = the
@@ -141,14 +146,32 @@ typedef struct {
                             Cuthill-McKee sweep */
   int32_t max_complexity_pct; /* operator-complexity budget x 100: the
                             hierarchy takes no aggregation level that would
-                            raise sum_l (nnz_l + n_l) / (nnz_0 + n_0) above
-                            it.  On expander-like complex networks the
-                            quotient graphs keep almost every edge, so the
-                            budget stops coarsening early; the deepest level
-                            then has no exact solve when it has more than
-                            4096 nodes, and every cycle ends there with one
+                            raise sum_l (nnz_l + n_l) / (nnz_a + n_a) above
+                            it, with a the first aggregated level (1 behind
+                            an elimination level, whose Schur complement the
+                            solver iterates on, else 0), nor one whose
+                            nnz + n exceeds 0.8 of the level it coarsens.
+                            On expander-like complex networks the quotient
+                            graphs keep almost every edge, so the budget
+                            stops coarsening early; the deepest level then
+                            has no exact solve when it has more than 4096
+                            nodes, and every cycle ends there with one
                             Jacobi step.  0 = default (200, i.e. 2.0),
-                            -1 = no budget (coarsen to coarsest_max) */
+                            -1 = no budget and no ratio limit (coarsen to
+                            coarsest_max) */
+  int32_t elim_degree;   /* largest degree of an eliminated node, 1 to
+                            CFC_ELIM_MAX_DEGREE; 0 = default (4).  The
+                            independent set is picked by degree, lowest
+                            first; removing a node of degree d joins its d
+                            neighbours pairwise (conductance w_a w_b / D_ff),
+                            which adds up to d (d - 3) matrix entries */
+  int32_t nest;          /* how far the locality numbering nests aggregates:
+                            1 = through every aggregation level down to
+                            coarsest_max, also those the budget leaves out;
+                            2 = through the levels the solver gets only;
+                            0 = auto (default): 2 when rows of more than
+                            256 entries hold a third or more of the
+                            entries (hub-dominated graphs), else 1 */
 } cfc_setup_params;
 
 typedef struct {
@@ -220,7 +243,8 @@ typedef struct {
   /* Elimination level (n_coarse < n, agg = NULL): rows [0, n_coarse) are
    * kept and are rows [0, n_coarse) of the next level, whose Laplacian is
    * the Schur complement; rows [n_coarse, n) are eliminated, each with at
-   * most two kept neighbours elim_nb[2 (r - n_coarse) + i] (-1 = none). */
+   * most CFC_ELIM_MAX_DEGREE kept neighbours
+   * elim_nb[CFC_ELIM_MAX_DEGREE (r - n_coarse) + i], ascending, then -1. */
   int32_t elimination;      /* 1 on an elimination level, else 0 */
   int32_t pad;
   const int32_t* elim_nb;

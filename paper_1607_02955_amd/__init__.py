@@ -92,12 +92,15 @@ def solve_params(tol=1e-6, precision=PREC_MIXED, block=0, max_refine=20, max_inn
 
 
 def setup_params(coarsest_max=512, agg_cap=8, test_vectors=8, relax_sweeps=8, omega=0.8,
-                 mu=1.5, seed=1, eliminate=1, device=1, order=0, max_complexity=0.0) -> _lib.SetupParams:
+                 mu=1.5, seed=1, eliminate=1, device=1, order=0, max_complexity=0.0,
+                 elim_degree=0, nest=0) -> _lib.SetupParams:
     """max_complexity: operator-complexity budget (0 = the default 2.0, a
-    negative value = none)."""
+    negative value = none).  elim_degree: largest degree of an eliminated
+    node (0 = the default 4).  nest: 1 = the numbering nests every
+    aggregation level, 2 = only the levels the solver gets, 0 = auto."""
     pct = 0 if max_complexity == 0 else (-1 if max_complexity < 0 else int(round(100 * max_complexity)))
     return _lib.SetupParams(coarsest_max, agg_cap, test_vectors, relax_sweeps, omega, mu, seed,
-                            eliminate, device, order, pct)
+                            eliminate, device, order, pct, elim_degree, nest)
 
 
 class Context:
@@ -214,7 +217,7 @@ class Graph:
                 "unit_weights": bool(i.unit_weights), "level_n": list(i.level_n[:L]),
                 "level_nnz": list(i.level_nnz[:L]), "operator_complexity": i.operator_complexity,
                 "setup_ms": i.setup_ms, "device_bytes": i.device_bytes, "max_degree": i.max_degree,
-                "eliminated": i.eliminated}
+                "eliminated": i.eliminated, "cycle_complexity": i.cycle_complexity}
 
     def node_map(self) -> np.ndarray:
         out = np.empty(self.n, np.int64)
@@ -244,7 +247,8 @@ class Graph:
         cp = arr(v.coarse_pinv, n * n, np.float64)
         out["coarse_pinv"] = None if cp is None else cp.reshape(n, n)
         out["elimination"] = bool(v.elimination)
-        out["elim_nb"] = arr(v.elim_nb, 2 * (n - nc), np.int32) if v.elimination else None
+        out["elim_nb"] = (arr(v.elim_nb, _lib.ELIM_MAX_DEGREE * (n - nc), np.int32)
+                          .reshape(n - nc, _lib.ELIM_MAX_DEGREE) if v.elimination else None)
         return out
 
     # ---- solves ----

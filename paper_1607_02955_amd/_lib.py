@@ -23,6 +23,7 @@ COL_OK, COL_NOT_CONVERGED, COL_DIVERGED, COL_SKIPPED = 0, 1, 2, 3
 LCC_ONLY, REJECT_PARALLEL = 1, 2
 PREC_MIXED, PREC_FP64 = 0, 1
 MAX_LEVELS = 32
+ELIM_MAX_DEGREE = 4  # neighbour slots of an eliminated row (CFC_ELIM_MAX_DEGREE)
 QUERY_SAMPLING, QUERY_JL = 0, 1
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -39,14 +40,15 @@ class GraphInfo(C.Structure):
                 ("unit_weights", C.c_int32), ("level_n", C.c_int64 * MAX_LEVELS),
                 ("level_nnz", C.c_int64 * MAX_LEVELS), ("operator_complexity", C.c_double),
                 ("setup_ms", C.c_double), ("device_bytes", C.c_uint64), ("max_degree", C.c_int32),
-                ("eliminated", C.c_int32)]
+                ("eliminated", C.c_int32), ("cycle_complexity", C.c_double)]
 
 
 class SetupParams(C.Structure):
     _fields_ = [("coarsest_max", C.c_int32), ("agg_cap", C.c_int32), ("test_vectors", C.c_int32),
                 ("relax_sweeps", C.c_int32), ("omega", C.c_double), ("mu", C.c_double),
                 ("seed", C.c_uint64), ("eliminate", C.c_int32), ("device", C.c_int32),
-                ("order", C.c_int32), ("max_complexity_pct", C.c_int32)]
+                ("order", C.c_int32), ("max_complexity_pct", C.c_int32),
+                ("elim_degree", C.c_int32), ("nest", C.c_int32)]
 
 
 class SolveParams(C.Structure):

@@ -199,6 +199,11 @@ int cfc_graph_get_info(const cfc_graph* gg, cfc_graph_info* out) {
     }
     den = (double)g->H.lv[0].nnz() + (double)g->H.lv[0].n;
     out->operator_complexity = den > 0 ? num / den : 1.0;
+    const size_t a = g->H.lv[0].nC > 0 ? 1 : 0;
+    double cnum = 0;
+    for (size_t l = a; l < g->H.lv.size(); ++l) cnum += (double)g->H.lv[l].nnz() + (double)g->H.lv[l].n;
+    const double cden = (double)g->H.lv[a].nnz() + (double)g->H.lv[a].n;
+    out->cycle_complexity = cden > 0 ? cnum / cden : 1.0;
     out->setup_ms = g->H.setup_ms;
   }
   if (g->D) out->device_bytes = g->D->bytes;

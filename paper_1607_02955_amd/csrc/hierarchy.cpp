@@ -41,6 +41,11 @@
 
 namespace cfc {
 
+// An aggregation level whose nnz + n exceeds this share of the level it
+// coarsens is not given to the solver (the quotient graph keeps almost every
+// edge: a cycle through it costs nearly a fine-level product and adds little).
+constexpr double kMaxLevelRatio = 0.8;
+
 cfc_setup_params default_setup() {
   cfc_setup_params p;
   p.coarsest_max = 512;
@@ -54,20 +59,23 @@ cfc_setup_params default_setup() {
   p.device = 1;
   p.order = 0;
   p.max_complexity_pct = 0;
+  p.elim_degree = 0;
+  p.nest = 0;
   return p;
 }
 
 namespace {
 
-// Choose an independent set of degree-1 nodes, then degree-2 nodes (in id
-// order), and form the Schur complement graph on the rest.  Returns false
-// when the mode's threshold is not met (mode 1: at least 5% of the nodes).
-bool eliminate(BLevel& B, int mode, BLevel& R) {
+// Choose an independent set of low-degree nodes, degree 1 first, then 2, up
+// to dmax (in id order within a degree), and form the Schur complement graph
+// on the rest.  Returns false when the mode's threshold is not met (mode 1:
+// at least 5% of the nodes).
+bool eliminate(BLevel& B, int mode, int dmax, BLevel& R) {
   const int64_t n = B.n;
   if (mode == 0 || n < 3) return false;
   std::vector<char> blocked(n, 0);
   std::vector<int32_t> F;
-  for (int d = 1; d <= 2; ++d)
+  for (int d = 1; d <= dmax; ++d)
     for (int64_t u = 0; u < n; ++u) {
       if (blocked[u] || B.rowptr[u + 1] - B.rowptr[u] != d) continue;
       if (n - (int64_t)F.size() <= 2) break;  // keep at least two nodes
@@ -95,12 +103,12 @@ bool eliminate(BLevel& B, int mode, BLevel& R) {
         row.emplace_back(B.cidx[v], B.w[e]);
         continue;
       }
-      if (B.rowptr[v + 1] - B.rowptr[v] != 2) continue;  // degree 1: the edge goes
-      // degree 2: series edge to v's other neighbour
-      const int32_t e0 = B.rowptr[v];
-      const int32_t o = B.col[e0] == u ? e0 + 1 : e0;
-      const double wa = B.w[e], wb = B.w[o];
-      row.emplace_back(B.cidx[B.col[o]], wa * wb / (wa + wb));
+      // eliminated neighbour v (all of its neighbours are kept): the Schur
+      // complement joins u to each other neighbour o of v with conductance
+      // w_uv w_vo / D_vv (a degree-1 v only lowers u's degree; degree 2 is
+      // the series rule)
+      for (int32_t o = B.rowptr[v]; o < B.rowptr[v + 1]; ++o)
+        if (B.col[o] != u) row.emplace_back(B.cidx[B.col[o]], B.w[e] * B.w[o] / B.deg[v]);
     }
     std::sort(row.begin(), row.end());
     const int64_t c = B.cidx[u];
@@ -427,6 +435,10 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
   if (!(p.omega > 0 && p.omega < 1)) fail(CFC_E_INVALID, "omega must be in (0, 1)");
   if (!(p.mu > 0 && p.mu < 2)) fail(CFC_E_INVALID, "mu must be in (0, 2)");
   if (p.eliminate < 0 || p.eliminate > 2) fail(CFC_E_INVALID, "eliminate must be 0, 1 or 2");
+  if (p.nest < 0 || p.nest > 2) fail(CFC_E_INVALID, "nest must be 0, 1 or 2");
+  if (p.elim_degree < 0 || p.elim_degree > CFC_ELIM_MAX_DEGREE)
+    fail(CFC_E_INVALID, "elim_degree must be in [0, " + std::to_string(CFC_ELIM_MAX_DEGREE) + "]");
+  const int elim_degree = p.elim_degree == 0 ? 4 : p.elim_degree;
   if (p.max_complexity_pct < -1 || (p.max_complexity_pct > 0 && p.max_complexity_pct < 100))
     fail(CFC_E_INVALID, "max_complexity_pct must be -1, 0 or at least 100");
   const double budget = p.max_complexity_pct < 0 ? 1e300 : (p.max_complexity_pct == 0 ? 2.0 : p.max_complexity_pct / 100.0);
@@ -438,7 +450,7 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
   B[0].deg = g.deg;
   {
     BLevel R;
-    if (B[0].n > p.coarsest_max && eliminate(B[0], p.eliminate, R)) B.push_back(std::move(R));
+    if (B[0].n > p.coarsest_max && eliminate(B[0], p.eliminate, elim_degree, R)) B.push_back(std::move(R));
   }
   if (p.device < 0 || p.device > 2) fail(CFC_E_INVALID, "device must be 0, 1 or 2");
   if (p.order < 0 || p.order > 3) fail(CFC_E_INVALID, "order must be 0, 1, 2 or 3");
@@ -452,18 +464,32 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
   auto ms_since = [](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
   };
-  // operator complexity so far, in units of level 0's nnz + n
-  const double unit0 = (double)B[0].col.size() + (double)B[0].n;
-  double oc = 0;
-  for (const BLevel& b : B) oc += ((double)b.col.size() + (double)b.n) / unit0;
-  // Levels past the budget are not given to the solver (L_keep), but without
-  // an elimination level aggregation goes on to coarsest_max anyway: the
-  // numbering nests aggregates of every level, a recursive clustering that
-  // keeps neighbours close (BA-100k: 369 us per operator product with it,
-  // 497 us with the numbering of the two levels the budget keeps).  Behind an
-  // elimination level the descending-degree numbering of the kept levels is
-  // the faster one (R-MAT-20: 2.78 ms against 3.05 ms with all levels).
-  const bool order_all = B.size() == 1;
+  // operator complexity of the aggregation levels, in units of nnz + n of
+  // the first level that is aggregated: behind an elimination level that is
+  // the Schur complement graph, on which the solver iterates (a cycle over
+  // the elimination level costs a fold and a back substitution, no product)
+  const double unit0 = (double)B.back().col.size() + (double)B.back().n;
+  double oc = 1.0;
+  // Levels past the budget are not given to the solver (L_keep), but
+  // aggregation may go on to coarsest_max anyway: the numbering then nests
+  // aggregates of every level, a recursive clustering that keeps neighbours
+  // close (BA-100k: 369 us per operator product with it, 497 us with the
+  // numbering of the two levels the budget keeps; with its degree-4 nodes
+  // eliminated, 69,754 against 63,321 solved columns/s).  On hub-dominated
+  // graphs, whose rows above 256 entries hold a third or more of the
+  // entries, the numbering of the kept levels alone is the faster one
+  // (R-MAT-20 Sampling: 6,293 against 5,526 columns/s with every level).
+  bool order_all = p.nest == 1;
+  if (p.nest == 0) {
+    int64_t hub_nnz = 0;
+    for (int64_t u = 0; u < g.n; ++u) {
+      const int64_t d = g.rowptr[u + 1] - g.rowptr[u];
+      if (d > 256) hub_nnz += d;
+    }
+    order_all = 3 * hub_nnz < (int64_t)g.col.size();
+  }
+  // an aggregation level must shrink nnz + n by a fifth (no limit without a budget)
+  const double ratio_cap = p.max_complexity_pct < 0 ? 1e300 : kMaxLevelRatio;
   int L_keep = 0;
   while (B.back().n > p.coarsest_max && (int)B.size() < CFC_MAX_LEVELS) {
     BLevel& F = B.back();
@@ -491,7 +517,8 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
       std::fprintf(stderr, "[cfc] setup level %d: n %lld nnz %zu -> %lld: aggregate %.0f ms, galerkin %.0f ms\n",
                    (int)B.size() - 1, (long long)F.n, F.col.size(), (long long)nc, t_agg, ms_since(ta));
     const double add = ((double)C.col.size() + (double)C.n) / unit0;
-    if (!L_keep && oc + add > budget) {  // the level would cost more than the budget allows
+    const double ratio = ((double)C.col.size() + (double)C.n) / ((double)F.col.size() + (double)F.n);
+    if (!L_keep && (oc + add > budget || ratio > ratio_cap)) {  // the level would cost more than the budget allows
       L_keep = (int)B.size();
       if (!order_all) break;
     }
@@ -610,8 +637,8 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
       const int64_t nc = F.nagg;
       O.nC = nc;
       O.fptr.assign(nc + 1, 0);
-      O.enb.assign(2 * (F.n - nc), -1);
-      O.ew.assign(2 * (F.n - nc), 0.0);
+      O.enb.assign(CFC_ELIM_MAX_DEGREE * (F.n - nc), -1);
+      O.ew.assign(CFC_ELIM_MAX_DEGREE * (F.n - nc), 0.0);
       O.einv.assign(F.n - nc, 0.0);
       std::vector<std::pair<int32_t, double>> fr;
       for (int64_t r = 0; r < F.n; ++r) {
@@ -627,10 +654,13 @@ void build_hierarchy_impl(Graph& g, const cfc_setup_params& p, bool on_device) {
           O.fptr[r + 1] = (int32_t)O.fcol.size();
         } else {
           const int64_t i = r - nc;
-          int k = 0;
-          for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e, ++k) {
-            O.enb[2 * i + k] = newid[l][F.col[e]];
-            O.ew[2 * i + k] = F.w[e];
+          fr.clear();
+          for (int32_t e = F.rowptr[old]; e < F.rowptr[old + 1]; ++e)
+            fr.emplace_back(newid[l][F.col[e]], F.w[e]);
+          std::sort(fr.begin(), fr.end());
+          for (size_t k = 0; k < fr.size(); ++k) {
+            O.enb[CFC_ELIM_MAX_DEGREE * i + k] = fr[k].first;
+            O.ew[CFC_ELIM_MAX_DEGREE * i + k] = fr[k].second;
           }
           O.einv[i] = 1.0 / F.deg[old];
         }

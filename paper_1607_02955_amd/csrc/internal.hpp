@@ -86,8 +86,8 @@ struct HostLevel {
   // Elimination level (nC > 0): rows [0, nC) are kept and are the next
   // level's rows; rows [nC, n) are eliminated.  Forward operator over kept
   // rows: fptr/fcol/fcoef (coefficient w_cf / d_f of eliminated row f);
-  // eliminated row f: kept neighbours enb[2 (f - nC) + i] (-1 = none) with
-  // conductances ew[...] and einv = 1 / d_f.
+  // eliminated row f: kept neighbours enb[CFC_ELIM_MAX_DEGREE (f - nC) + i]
+  // (ascending, then -1) with conductances ew[...] and einv = 1 / d_f.
   int64_t nC = 0;
   std::vector<int32_t> fptr, fcol, enb;
   std::vector<double> fcoef, ew, einv;

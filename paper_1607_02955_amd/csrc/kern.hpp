@@ -9,6 +9,7 @@ namespace cfc {
 
 constexpr int kBlock = 256;      // threads per workgroup
 constexpr int kMaxGrid = 2048;   // workgroups of kernels that emit partial sums
+constexpr int kElimDeg = 4;      // neighbour slots of an eliminated row
 
 // One multigrid level as the kernels see it (element type T chosen by table).
 struct LevelArgs {
@@ -43,8 +44,9 @@ struct LevelArgs {
   // segments themselves)
   void* hsum = nullptr;
   // Elimination level (nC > 0): rows [nC, n) are eliminated; row nC + i has
-  // kept neighbours enb[2i], enb[2i+1] (-1 = none), conductances ew[2i..]
-  // and einv[i] = 1 / D_ii (element type T).
+  // kept neighbours enb[kElimDeg i + j] (j < kElimDeg; the neighbours first,
+  // then -1), conductances ew[kElimDeg i + j] and einv[i] = 1 / D_ii
+  // (element type T).  enb is 16-byte aligned.
   int nC = 0;
   const int* enb = nullptr;
   const void* ew = nullptr;

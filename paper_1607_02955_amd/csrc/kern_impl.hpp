@@ -1148,16 +1148,17 @@ __global__ __launch_bounds__(kBlock) void k_elim_back(LevelArgs L, const T* __re
     Vec<T, V> zu;
     if (u >= L.nC) {
       const int i = u - L.nC;
-      const int a = L.enb[2 * i], b = L.enb[2 * i + 1];
-      const T wa = ew[2 * i], di = einv[i];
-      const Vec<T, V> za = zrow(a);
+      const int4 nb = reinterpret_cast<const int4*>(L.enb)[i];
+      const int a[kElimDeg] = {nb.x, nb.y, nb.z, nb.w};
+      const T di = einv[i];
+      zu = ru;
 #pragma unroll
-      for (int k = 0; k < V; ++k) zu.v[k] = ru.v[k] + wa * za.v[k];
-      if (b >= 0) {
-        const T wb = ew[2 * i + 1];
-        const Vec<T, V> zb = zrow(b);
+      for (int j = 0; j < kElimDeg; ++j) {
+        if (a[j] < 0) break;  // neighbours first, then -1
+        const T wa = ew[kElimDeg * i + j];
+        const Vec<T, V> za = zrow(a[j]);
 #pragma unroll
-        for (int k = 0; k < V; ++k) zu.v[k] += wb * zb.v[k];
+        for (int k = 0; k < V; ++k) zu.v[k] += wa * za.v[k];
       }
 #pragma unroll
       for (int k = 0; k < V; ++k) zu.v[k] *= di;

@@ -19,6 +19,8 @@
 #include "kern.hpp"
 #include "solver.hpp"
 
+static_assert(cfc::kElimDeg == CFC_ELIM_MAX_DEGREE, "eliminated-row neighbour slots");
+
 namespace cfc {
 
 // ---------------------------------------------------------------------------
@@ -352,9 +354,10 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
   const bool exact = nuse == w.nlev && g->D->nc > 0;  // deepest visited level is the true coarsest
   const size_t es = w.fp64 ? 8 : 4;
   const double nw = (double)w.W * es;
-  const DevLevel& d0 = g->D->lv[0];
+  const int b0 = base;  // the level the CG runs on
+  const DevLevel& d0 = g->D->lv[b0];
   const void* rsrc = update ? r_out : r_in;
-  if ((L == 1 && !exact) || schur) {
+  if (jac_top) {
     // depth one: Jacobi-preconditioned CG on the base level, z = S r
     const DevLevel& db = g->D->lv[base];
     const LevelArgs& lb = w.la[base];
@@ -376,13 +379,13 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     g_rz = grid_for(db.n, k.rg);
     return;
   }
-  if (d0.nC > 0 && L >= 2) {
+  if (!schur && d0.nC > 0 && L >= 2) {
     vcycle_elim(update, first_x, r_in, r_out);
     return;
   }
-  if (L == 1) {  // single-level hierarchy: the preconditioner is L^+ itself
+  if (L - b0 == 1) {  // the base level is the coarsest: the preconditioner is its L^+
     if (update) {
-      LevelArgs a = w.la[0];
+      LevelArgs a = w.la[b0];
       a.nagg = 0;
       k.update_restrict(a, r_in, w.q.p, w.p.p, w.x.p, r_out, nullptr, w.scal.as<double>(), first_x,
                         1, w.part_ptr(P_RR), w.part_ptr(P_CS), xfu ? 1 : 0, s);
@@ -397,17 +400,17 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     return;
   }
   if (update) prof_begin(K_RESTRICT0);
-  k.update_restrict(w.la[0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.b[1].p, w.scal.as<double>(),
+  k.update_restrict(w.la[b0], r_in, w.q.p, w.p.p, w.x.p, r_out, w.b[b0 + 1].p, w.scal.as<double>(),
                     first_x, update ? 1 : 0, w.part_ptr(P_RR), w.part_ptr(P_CS), xfu ? 1 : 0, s);
   const double rb = d0.n * nw * (update ? upd_blocks(first_x) : 1) + d0.nagg * nw +
                     mat_bytes(d0, !d0.unit, es) + 4.0 * (d0.nagg + 1);
   if (update) {
     prof_end(K_RESTRICT0, rb);
-    g_rr = k.rows_grid(w.la[0], d0.nagg);
+    g_rr = k.rows_grid(w.la[b0], d0.nagg);
     g_cs = xfu ? 0 : g_rr;
   }
   bytes += rb;
-  for (int l = 1; l + 1 < L; ++l) {
+  for (int l = b0 + 1; l + 1 < L; ++l) {
     const DevLevel& d = g->D->lv[l];
     k.restrict_(w.la[l], w.b[l].p, w.b[l + 1].p, s);
     bytes += d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * (d.nagg + 1);
@@ -421,16 +424,16 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
     k.jacobi(w.la[L - 1], w.b[L - 1].p, w.xl[L - 1].p, nullptr, 0, s);
     bytes += 2.0 * d.n * nw + es * d.n;
   }
-  for (int l = L - 2; l >= 1; --l) {
+  for (int l = L - 2; l >= b0 + 1; --l) {
     const DevLevel& d = g->D->lv[l];
     k.prolong_smooth(w.la[l], w.b[l].p, w.xl[l + 1].p, w.xl[l].p, nullptr, s);
     bytes += 2.0 * d.n * nw + d.nagg * nw + mat_bytes(d, true, es) + 4.0 * d.n;
   }
   prof_begin(K_PROLONG0);
-  k.prolong_smooth(w.la[0], rsrc, w.xl[1].p, w.z.p, w.part_ptr(P_RZ), s);
+  k.prolong_smooth(w.la[b0], rsrc, w.xl[b0 + 1].p, w.z.p, w.part_ptr(P_RZ), s);
   const double pb = 2.0 * d0.n * nw + d0.nagg * nw + mat_bytes(d0, !d0.unit, es) + 4.0 * d0.n;
   prof_end(K_PROLONG0, pb);
-  g_rz = k.rows_grid(w.la[0], d0.n);
+  g_rz = k.rows_grid(w.la[b0], d0.n);
   bytes += pb;
 }
 
@@ -560,7 +563,7 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
   // depth one: z = S r_in is formed inside the product kernel
   // (or gathered from its bfloat16 copy in ws.z)
   // one Jacobi step as the whole preconditioner (no exact solve on level 0)
-  const bool jac = (nuse == 1 && (w.nlev > 1 || g->D->nc == 0)) || schur;
+  const bool jac = jac_top;
   k.spmm_pq(w.la[base], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, xfu ? w.x.p : nullptr,
             w.scal.as<double>(), first, w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
   const double sb = (bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
@@ -825,12 +828,13 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   const bool smoothed = nuse < ws->nlev || g->D->nc == 0;
   const bool jac1 = nuse == 1 && smoothed;
   const bool elim2 = g->D->lv[0].nC > 0 && nuse == 2 && smoothed;
-  // An elimination level with one Jacobi step behind it: CG on the Schur
+  // An elimination level and at least one level behind it: CG on the Schur
   // complement (CFC_SCHUR=0 keeps CG on level 0 with the elimination inside
   // the preconditioner).
   const char* sc = std::getenv("CFC_SCHUR");
-  schur = elim2 && !(sc && sc[0] == '0');
+  schur = g->D->lv[0].nC > 0 && nuse >= 2 && !(sc && sc[0] == '0');
   base = schur ? 1 : 0;
+  jac_top = nuse - base == 1 && smoothed;
   bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
   // The product kernel carries the x updates (CFC_FUSE_X=0 keeps them in
   // the update kernel).

@@ -55,12 +55,14 @@ struct Solver {
   int g_rz = 0, g_rr = 0, g_cs = 0;
   int nuse = 1;  // V-cycle depth
   bool bfz = false;  // Jacobi paths: z = M^-1 r stored as bfloat16 in ws->z
-  // Schur mode (an elimination level with one Jacobi step behind it): the
-  // inner CG runs on level 1, the Schur complement S, preconditioned by one
-  // Jacobi step; pcg() folds the level-0 residual onto the kept rows first
-  // and back-substitutes the eliminated rows of the correction after.
+  // Schur mode (level 0 an elimination level, depth two or more): the inner
+  // CG runs on level 1, the Schur complement S, preconditioned by one
+  // Jacobi step (depth two) or by the V-cycle from level 1; pcg() folds the
+  // level-0 residual onto the kept rows first and back-substitutes the
+  // eliminated rows of the correction after.
   bool schur = false;
   int base = 0;  // level the inner CG runs on (1 in Schur mode)
+  bool jac_top = false;  // the preconditioner is one Jacobi step on level `base`
   void* r0 = nullptr;  // the inner CG's initial residual (ws.ra, or ws.rt in Schur mode)
   bool xfu = false;  // x updates applied by the product kernel
   bool multi_step = false;  // a block of this solve took more than one refinement step

@@ -158,12 +158,12 @@ def test_device_aggregation(ctx, maker):
 
 
 def test_budget_truncated_hierarchy(ctx):
-    """Under the default complexity budget a Barabasi-Albert graph keeps one
-    aggregation level of more than 4096 nodes and no exact coarsest solve:
-    the full-depth cycle ends there with a Jacobi step, and every depth still
-    gives the oracle's resistances."""
+    """Under the default complexity budget a Barabasi-Albert graph (without
+    an elimination level) keeps one aggregation level of more than 4096
+    nodes and no exact coarsest solve: the full-depth cycle ends there with a
+    Jacobi step, and every depth still gives the oracle's resistances."""
     eg = synth.barabasi_albert(15000, 4, seed=12)
-    g = load(ctx, eg, coarsest_max=64)
+    g = load(ctx, eg, coarsest_max=64, eliminate=0)
     info = g.info()
     say("budget", info["levels"], info["level_n"], info["operator_complexity"])
     assert info["operator_complexity"] <= 2.0 and info["level_n"][-1] > 4096
@@ -388,7 +388,7 @@ def leafy_graph(seed=31, n=3000):
 @pytest.mark.parametrize("W,prec", [(64, 0), (256, 1), (32, 0)])
 def test_elimination_level_all_depths(ctx, W, prec):
     """An elimination level (exact Schur complement of an independent set of
-    degree-1/2 nodes) in front of the aggregation levels: every V-cycle depth
+    nodes of degree 1 to 4) in front of the aggregation levels: every V-cycle depth
     and the full exact path give the oracle's resistances."""
     eg = leafy_graph(seed=W)
     say("elimination", W, prec, eg.n, eg.m)
@@ -411,29 +411,37 @@ def test_elimination_level_all_depths(ctx, W, prec):
 
 @pytest.mark.parametrize("W", [64, 256])
 def test_schur_cg_matches_level0_cg(ctx, W, monkeypatch):
-    """An elimination level with one Jacobi step behind it: CG on the Schur
-    complement (the residual folded onto the kept rows, the eliminated rows
-    back-substituted) and CG on level 0 with the elimination inside the
-    preconditioner give the oracle's resistances in about as many
-    iterations, also on an R-MAT graph whose hubs are heavy rows of the
-    Schur complement, and with the iterations replayed from a HIP graph."""
-    for name, eg in [("leafy", leafy_graph(seed=W + 1)), ("rmat", synth.rmat(11, seed=W))]:
+    """An elimination level with one Jacobi step or a V-cycle behind it: CG
+    on the Schur complement (the residual folded onto the kept rows, the
+    eliminated rows back-substituted) and CG on level 0 with the elimination
+    inside the preconditioner give the oracle's resistances in about as
+    many iterations, also on an R-MAT graph whose hubs are heavy rows of the
+    Schur complement, on a road grid whose degree-3 and degree-4 nodes are
+    eliminated (fill between their neighbours), and with the iterations
+    replayed from a HIP graph."""
+    for name, eg in [("leafy", leafy_graph(seed=W + 1)), ("rmat", synth.rmat(11, seed=W)),
+                     ("road", synth.road_grid(40, seed=W))]:
         g = load(ctx, eg, coarsest_max=64, eliminate=2, max_complexity=-1)
+        lv0 = g.level(0)
         assert g.info()["eliminated"] > 0
+        if name == "road":
+            assert (lv0["elim_nb"] >= 0).sum(axis=1).max() == 4
         _, Rm = dense_R(eg)
         rng = np.random.default_rng(W)
         s = rng.integers(0, eg.n, 2 * W + 5)
         t = rng.integers(0, eg.n, 2 * W + 5)
-        its = {}
-        for mode in ("1", "0"):
-            monkeypatch.setenv("CFC_SCHUR", mode)
-            for graph in (0, 1):
-                r, st = g.resistance(s, t, block=W, tol=1e-8, levels=2, use_graph=graph, stats=True,
-                                     max_inner=3000)
-                say("schur", name, W, mode, graph, st["inner_iters"], st["refine_steps"], st["max_rel_residual"])
-                np.testing.assert_allclose(r, Rm[s, t], rtol=1e-7, atol=1e-12)
-                its[mode, graph] = st["inner_iters"]
-        assert its["1", 0] <= 1.25 * its["0", 0] + 4, its
+        for depth in (2, 3, 0):
+            its = {}
+            for mode in ("1", "0"):
+                monkeypatch.setenv("CFC_SCHUR", mode)
+                for graph in (0, 1):
+                    r, st = g.resistance(s, t, block=W, tol=1e-8, levels=depth, use_graph=graph,
+                                         stats=True, max_inner=3000)
+                    say("schur", name, W, depth, mode, graph, st["inner_iters"], st["refine_steps"],
+                        st["max_rel_residual"])
+                    np.testing.assert_allclose(r, Rm[s, t], rtol=1e-7, atol=1e-12)
+                    its[mode, graph] = st["inner_iters"]
+            assert its["1", 0] <= 1.25 * its["0", 0] + 4, its
 
 
 @pytest.mark.parametrize("case", ["depth1_hubs", "elim_depth2"])

@@ -91,9 +91,9 @@ def _level_laplacian(lv):
     return L
 
 
-def _check_elimination_level(lv, nxt):
+def _check_elimination_level(lv, nxt, max_degree=4):
     """Kept rows first; eliminated rows form an independent set of degree 1
-    or 2; the next level is the Schur complement on the kept rows."""
+    to 4; the next level is the Schur complement on the kept rows."""
     n, nc = lv["n"], lv["n_coarse"]
     assert l_ok(nc, n) and nxt["n"] == nc
     Lf = _level_laplacian(lv)
@@ -101,10 +101,12 @@ def _check_elimination_level(lv, nxt):
     LFF = Lf[np.ix_(F, F)]
     np.testing.assert_allclose(LFF, np.diag(np.diag(LFF)), atol=0)  # independent set
     deg = np.diff(lv["row_ptr"])[F]
-    assert deg.min() >= 1 and deg.max() <= 2
-    nb = lv["elim_nb"].reshape(-1, 2)
+    assert deg.min() >= 1 and deg.max() <= max_degree
+    nb = lv["elim_nb"]
+    assert nb.shape == (n - nc, 4)
     for i, r in enumerate(F):
-        got = sorted(x for x in nb[i] if x >= 0)
+        got = [x for x in nb[i] if x >= 0]
+        assert nb[i].tolist() == got + [-1] * (4 - len(got))  # neighbours first, then -1
         assert got == sorted(lv["col"][lv["row_ptr"][r]:lv["row_ptr"][r + 1]].tolist())
         assert max(got) < nc
     C = np.arange(nc)
@@ -125,11 +127,12 @@ def l_ok(nc, n):
     lambda: synth.star_graph(2000),
     lambda: synth.random_connected(1500, 2200, seed=9),
 ])
-@pytest.mark.parametrize("elim", [0, 2])
-def test_hierarchy_invariants(hctx, maker, elim):
+@pytest.mark.parametrize("elim,elim_degree", [(0, 0), (2, 2), (2, 0)], ids=["noelim", "deg2", "deg4"])
+def test_hierarchy_invariants(hctx, maker, elim, elim_degree):
     eg = maker()
     g = cfc.Graph.from_edgelist(hctx, eg)
-    g.build_hierarchy(coarsest_max=128, eliminate=elim, max_complexity=-1)  # every level
+    g.build_hierarchy(coarsest_max=128, eliminate=elim, elim_degree=elim_degree,
+                      max_complexity=-1)  # every level
     info = g.info()
     L = info["levels"]
     assert L >= 2 and info["level_n"][-1] <= 128
@@ -145,7 +148,7 @@ def test_hierarchy_invariants(hctx, maker, elim):
         lv = g.level(l)
         nxt = g.level(l + 1)
         if lv["elimination"]:
-            _check_elimination_level(lv, nxt)
+            _check_elimination_level(lv, nxt, elim_degree or 4)
             continue
         agg, ap = lv["agg"], lv["agg_ptr"]
         assert ap[0] == 0 and ap[-1] == lv["n"] and np.all(np.diff(ap) >= 1)
@@ -169,24 +172,49 @@ def test_hierarchy_invariants(hctx, maker, elim):
     np.testing.assert_allclose(Pc, R.pinv(Lc), atol=1e-8 * max(1.0, np.abs(Pc).max()))
 
 
+def _budget_complexity(g):
+    """sum_l (nnz_l + n_l) over the aggregation levels, in units of the first
+    aggregated level (level 1 behind an elimination level)."""
+    info = g.info()
+    a = 1 if info["levels"] > 1 and g.level(0)["elimination"] else 0
+    u = [info["level_nnz"][l] + info["level_n"][l] for l in range(info["levels"])]
+    assert info["cycle_complexity"] == pytest.approx(sum(u[a:]) / u[a], rel=1e-12)
+    ratios = [u[l + 1] / u[l] for l in range(a, info["levels"] - 1)]
+    return sum(u[a:]) / u[a], ratios
+
+
 def test_complexity_budget(hctx):
-    """The default budget keeps sum_l (nnz_l + n_l) / (nnz_0 + n_0) <= 2: on a
+    """The default budget keeps the aggregation levels' complexity <= 2: on a
     Barabasi-Albert graph the quotient graphs keep almost every edge, so it
     stops after one aggregation level, above 4096 nodes here and so with no
-    exact coarsest solve; a road grid coarsens as far as without a budget."""
+    exact coarsest solve; a road grid coarsens as far as without a budget.
+    Behind an elimination level the budget is counted from the Schur
+    complement graph."""
     ba = synth.barabasi_albert(20000, 4, seed=3)
-    full = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, max_complexity=-1).info()
-    assert full["operator_complexity"] > 2.0
-    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128)
+    full = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, eliminate=0,
+                                                             max_complexity=-1)
+    assert full.info()["operator_complexity"] > 2.0
+    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, eliminate=0)
     info = g.info()
-    assert info["operator_complexity"] <= 2.0 and 2 <= info["levels"] < full["levels"]
+    assert info["operator_complexity"] <= 2.0 and 2 <= info["levels"] < full.info()["levels"]
     assert info["level_n"][-1] > 4096 and g.level(info["levels"] - 1)["coarse_pinv"] is None
-    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, max_complexity=3.0)
+    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, eliminate=0, max_complexity=3.0)
     assert g.info()["operator_complexity"] <= 3.0
+    # degree-4 nodes eliminated first (a third of this graph's nodes); the
+    # quotient graph of their Schur complement keeps over 0.8 of its size,
+    # so no aggregation level follows
+    g = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128)
+    assert g.level(0)["elimination"] and g.info()["levels"] == 2
+    assert _budget_complexity(g) == (1.0, [])
+    nob = cfc.Graph.from_edgelist(hctx, ba).build_hierarchy(coarsest_max=128, max_complexity=-1)
+    assert _budget_complexity(nob)[1][0] > 0.8
     rd = synth.road_grid(100, seed=2)
-    a = cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(coarsest_max=64).info()
-    b = cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(coarsest_max=64, max_complexity=-1).info()
-    assert a["levels"] == b["levels"] and a["operator_complexity"] <= 2.0
+    for elim in (0, 1):
+        a = cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(coarsest_max=64, eliminate=elim)
+        b = cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(coarsest_max=64, eliminate=elim,
+                                                              max_complexity=-1)
+        oc, ratios = _budget_complexity(a)
+        assert a.info()["levels"] == b.info()["levels"] and oc <= 2.0 and max(ratios) <= 0.8
     with pytest.raises(cfc.CfcError, match="INVALID"):
         cfc.Graph.from_edgelist(hctx, rd).build_hierarchy(max_complexity=0.5)
 
@@ -263,8 +291,9 @@ def test_locality_orders_give_valid_nested_hierarchies(hctx, order):
     p = lv0["perm"]
     np.testing.assert_allclose(_level_laplacian(lv0)[np.ix_(p, p)], Lin, atol=1e-12)
     for l in range(g.info()["levels"] - 1):
-        agg = g.level(l)["agg"]
-        assert np.all(np.diff(agg) >= 0)
+        lv = g.level(l)
+        if not lv["elimination"]:
+            assert np.all(np.diff(lv["agg"]) >= 0)
     if order == 3:  # hubs first: row 0 holds a node of maximum degree
         deg = np.diff(LAP.of(eg).indptr)
         assert deg[np.argsort(p)[0]] == deg.max()
@@ -273,6 +302,7 @@ def test_locality_orders_give_valid_nested_hierarchies(hctx, order):
 def test_setup_param_errors_enums(hctx):
     eg = synth.path_graph(10)
     g = cfc.Graph.from_edgelist(hctx, eg)
-    for kw in ({"order": 4}, {"eliminate": 3}, {"device": 3}):
+    for kw in ({"order": 4}, {"eliminate": 3}, {"device": 3}, {"elim_degree": 5},
+               {"elim_degree": -1}):
         with pytest.raises(cfc.CfcError):
             g.build_hierarchy(**kw)
