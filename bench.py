@@ -561,14 +561,14 @@ def measure(workload, args, extras=True, ctx=None):
         agg["maxrel"] = max(agg["maxrel"], st["max_rel_residual"])
         agg["W"] = st["block_width"]
         agg["depth"] = st["levels_used"]
+        agg["zf"] = st["z_format"]
         progress(f"step {i + 1}/{args.steps}: {cols} columns")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = agg["cols"] / dt
-    # z is stored as bfloat16 when the preconditioner is one Jacobi sweep
-    # (depth 1) or the elimination level plus one sweep (depth 2 behind it)
-    bfz = os.environ.get("CFC_BF16_Z", "1") != "0" and (
-        agg["depth"] == 1 or (agg["depth"] == 2 and info["eliminated"] > 0))
+    # the preconditioned residual that the operator product gathers is
+    # stored as bfloat16 or FP8 on the Jacobi-preconditioned paths
+    zlabel = {1: " (z stored bf16)", 2: " (z stored fp8 e4m3, per-row-slice scale)"}.get(agg.get("zf", 0), "")
     roof = None
     dom = max(range(3), key=lambda j: agg["kms"][j])
     if agg["kl"][dom]:
@@ -596,7 +596,7 @@ def measure(workload, args, extras=True, ctx=None):
         "metric": "solved RHS/s at 1e-6 rel. residual", "value": round(value, 2),
         "unit": "solved RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt * 1e3 / args.steps, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": ("f32+f64 (z stored bf16)" if bfz else "f32+f64") if prec == 0 else "f64",
+        "vs_baseline": None, "dtype": "f32+f64" + zlabel if prec == 0 else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "graph": eg.name, "n": eg.n, "m": eg.m,
                    "estimator": spec["kind"], "k": spec.get("k"), "block_width": agg["W"],

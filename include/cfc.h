@@ -212,7 +212,10 @@ typedef struct {
   int32_t block_width;    /* W used */
   int32_t precision;
   int32_t levels_used;    /* V-cycle depth used */
-  int32_t pad;
+  int32_t z_format;       /* storage of the preconditioned residual that the
+                             operator product gathers: 0 = the inner
+                             precision, 1 = bfloat16, 2 = FP8 (e4m3) with one
+                             scale per row and column slice */
   double max_rel_residual;/* largest final ||b - L x|| / ||b|| (FP64) */
   double solve_ms;        /* device time of the solve phase (HIP events) */
   double model_bytes;     /* algorithmic HBM bytes of the solve phase */

@@ -61,7 +61,7 @@ class SolveParams(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("columns", C.c_int64), ("converged", C.c_int64), ("inner_iters", C.c_int64),
                 ("refine_steps", C.c_int64), ("blocks", C.c_int64), ("block_width", C.c_int32),
-                ("precision", C.c_int32), ("levels_used", C.c_int32), ("pad", C.c_int32),
+                ("precision", C.c_int32), ("levels_used", C.c_int32), ("z_format", C.c_int32),
                 ("max_rel_residual", C.c_double), ("solve_ms", C.c_double),
                 ("model_bytes", C.c_double), ("kernel_ms", C.c_double * 3),
                 ("kernel_bytes", C.c_double * 3), ("kernel_launches", C.c_int64 * 3)]

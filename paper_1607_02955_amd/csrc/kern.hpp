@@ -11,6 +11,16 @@ constexpr int kBlock = 256;      // threads per workgroup
 constexpr int kMaxGrid = 2048;   // workgroups of kernels that emit partial sums
 constexpr int kElimDeg = 4;      // neighbour slots of an eliminated row
 
+// Column slices of a W-wide block (see Shape in kern_impl.hpp).
+__host__ __device__ constexpr int slices_of(int W) {
+  return W >= 512 ? 8 : (W >= 256 ? 4 : (W >= 32 ? W / 32 : 1));
+}
+// Byte offset of the per-row-slice scales (float[n][slices_of(W)]) after the
+// n x W bytes of an FP8 copy of z.
+__host__ __device__ constexpr size_t f8_scale_off(int n, int W) {
+  return ((size_t)n * (size_t)W + 255) & ~size_t(255);
+}
+
 // One multigrid level as the kernels see it (element type T chosen by table).
 struct LevelArgs {
   int n = 0;        // rows
@@ -76,7 +86,8 @@ struct KernTable {
   int (*rows_grid)(const LevelArgs&, int units);
   // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q.
   // jac = 1: z is passed as r and formed as S r on the fly; jac = 2: z is
-  // its bfloat16 copy (uint16[n][W]).  x (nullable): also apply the previous
+  // its bfloat16 copy (uint16[n][W]); jac = 3: its FP8 copy (uint8[n][W],
+  // then float scales[n][slices] at f8_scale_off(n, W)).  x (nullable): also apply the previous
   // iteration's x += alpha p (not on the first iteration).
   void (*spmm_pq)(const LevelArgs&, const void* z, void* p, void* q, void* x, const double* scal,
                   int first, double* part, int jac, hipStream_t);
@@ -93,16 +104,18 @@ struct KernTable {
   // Prolong + post-smooth: xt = S b + mu xc[agg], x = xt + S (b - L xt); partial b.x if part
   void (*prolong_smooth)(const LevelArgs&, const void* b, const void* xc, void* x,
                          double* part_rz, hipStream_t);
-  // x = S b (Jacobi step from zero) on a level; partial b.x if part; bf = 1
-  // stores x as bfloat16 (requires part)
-  void (*jacobi)(const LevelArgs&, const void* b, void* x, double* part, int bf, hipStream_t);
+  // x = S b (Jacobi step from zero) on a level; partial b.x if part; zf = 1
+  // stores x as bfloat16, zf = 2 as FP8 with per-row-slice scales (both
+  // require part)
+  void (*jacobi)(const LevelArgs&, const void* b, void* x, double* part, int zf, hipStream_t);
   // Jacobi-PCG update on level 0: r_out = r_in - alpha q, x += alpha p,
-  // z = S r_out; partials |r_out|^2, sum x, r_out.z; bf = 1 stores z as
-  // bfloat16 (z non-null); xf = 1 leaves x to spmm_pq (x = 0 on the first
-  // iteration, no sum-x partials) and does not read p
+  // z = S r_out; partials |r_out|^2, sum x, r_out.z; zf = 1 stores z as
+  // bfloat16, zf = 2 as FP8 with per-row-slice scales (z non-null); xf = 1
+  // leaves x to spmm_pq (x = 0 on the first iteration, no sum-x partials)
+  // and does not read p
   void (*update_jacobi)(const LevelArgs&, const void* r_in, const void* q, const void* p, void* x,
                         void* r_out, void* z, const double* scal, int first, double* prr,
-                        double* pcs, double* prz, int bf, int xf, hipStream_t);
+                        double* pcs, double* prz, int zf, int xf, hipStream_t);
   // x += alpha p over n level-0 rows, partial column sums of x (grid
   // grid_for(n, rg)): the last update when spmm_pq carries them
   void (*xfinal)(int n, void* x, const void* p, const double* scal, double* pcs, hipStream_t);

@@ -37,7 +37,7 @@ template <int W> struct Shape {
   // are 128 B too: on R-MAT-20 at W = 256, 4 slices of 64 columns measured
   // 3.05 ms per product against 3.98 ms for 8 slices of 32 (random 64-byte
   // reads use HBM worse than 128-byte ones)
-  static constexpr int NS = W >= 512 ? 8 : (W >= 256 ? 4 : (W >= 32 ? W / 32 : 1));
+  static constexpr int NS = slices_of(W);
   static constexpr int WS = W / NS;           // columns per slice
   static constexpr int V = WS >= 4 ? 4 : 1;   // columns per lane
   static constexpr int LPR = WS / V;          // lanes per row group
@@ -96,6 +96,69 @@ __device__ __forceinline__ Vec<T, V> ld_bf(const bf16_t* p) {
 #pragma unroll
   for (int i = 0; i < V; ++i) r.v[i] = T(bf2f(h.v[i]));
   return r;
+}
+
+// FP8 storage of z (OCP e4m3, finite range +-448) on the same paths: each
+// row's column slice (the LPR lanes of one row group) shares one FP32 scale
+// max|z| / 448, stored after the n x W bytes (float[n][NS] at
+// f8_scale_off(n, W)).  As with bfloat16, z is rounded once where it is
+// formed and every later use sees the dequantised value; a gathered slice
+// row is WS bytes plus its scale.
+typedef unsigned char f8_t;
+constexpr float kF8Max = 448.0f;
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ld_f8(const f8_t* p, float scale) {
+  Vec<T, V> r;
+  if constexpr (V == 4) {
+    const int w = *reinterpret_cast<const int*>(p);
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+    r.v[0] = T(lo[0] * scale);
+    r.v[1] = T(lo[1] * scale);
+    r.v[2] = T(hi[0] * scale);
+    r.v[3] = T(hi[1] * scale);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = T(__builtin_amdgcn_cvt_f32_fp8(int(p[i]), 0) * scale);
+  }
+  return r;
+}
+
+// Round a row group's slice of z to FP8: the scale is the largest finite
+// |z| of the slice over 448 (slices whose largest |z| is below 1e-30 are
+// stored as zeros); values are clamped to +-448 (NaN stays NaN) and z is
+// replaced by the dequantised values.  Lane 0 of the row group stores the
+// scale.
+template <typename T, int W>
+__device__ __forceinline__ void st_f8(Vec<T, Shape<W>::V>& z, f8_t* dst, float* sc_dst) {
+  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V;
+  float m = 0.0f;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const float a = fabsf(float(z.v[i]));
+    if (a <= 3.0e38f) m = fmaxf(m, a);
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  const float inv = m > 1e-30f ? kF8Max / m : 0.0f;
+  const float scale = m > 1e-30f ? m / kF8Max : 0.0f;
+  float y[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const float t = float(z.v[i]) * inv;
+    y[i] = t > kF8Max ? kF8Max : (t < -kF8Max ? -kF8Max : t);
+  }
+  if constexpr (V == 4) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], w, true);
+    *reinterpret_cast<int*>(dst) = w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) dst[i] = f8_t(__builtin_amdgcn_cvt_pk_fp8_f32(y[i], 0.0f, 0, false) & 0xff);
+  }
+  if (threadIdx.x % LPR == 0) *sc_dst = scale;
+  z = ld_f8<T, V>(dst, scale);
 }
 
 // Streaming (non-temporal) row access for values read or written once per
@@ -256,7 +319,8 @@ __device__ __forceinline__ void add_heavy(const LevelArgs& L, int u, T* nb, int 
 // hpart[seg] = sum_e w_e f(col_e) with f chosen by KIND.
 enum HeavyKind {
   HK_SPMM = 0, HK_RESTRICT = 1, HK_RESTRICT_UPD = 2, HK_PROLONG = 3, HK_RES64 = 4, HK_BF16 = 5,
-  HK_RES32 = 6  // T = double, the gathered block is FP32
+  HK_RES32 = 6,  // T = double, the gathered block is FP32
+  HK_F8 = 7      // the gathered block is FP8 with per-row-slice scales
 };
 
 template <typename T, int W, int KIND>
@@ -271,6 +335,9 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
   const T* w = static_cast<const T*>(L.hw);
   const T* sd = static_cast<const T*>(L.sd);
   const T mu = T(L.mu);
+  const float* zsc = KIND == HK_F8 ? reinterpret_cast<const float*>(
+                                         reinterpret_cast<const f8_t*>(a) + f8_scale_off(L.n, W))
+                                   : nullptr;
   T alpha[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) alpha[i] = KIND == HK_RESTRICT_UPD ? T(scal[S_ALPHA * W + c0 + i]) : T(0);
@@ -279,6 +346,9 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
 #pragma unroll
     for (int i = 0; i < V; ++i) nb[i] = 0;
     gather_acc<T, W>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
+      if constexpr (KIND == HK_F8)
+        return ld_f8<T, V>(reinterpret_cast<const f8_t*>(a) + (size_t)v * W + c0,
+                           zsc[(size_t)v * Shape<W>::NS + slice]);
       if constexpr (KIND == HK_BF16)
         return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(a) + (size_t)v * W + c0);
       if constexpr (KIND == HK_RES32) {
@@ -364,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_heavy_sum(LevelArgs L) {
 // PCG step on level 0: q = L z + beta q, p = z + beta p; partial p.q.
 // JAC = 1: the preconditioner is one Jacobi step, and z = S r is formed on
 // the fly from the residual passed in place of z (saves storing z).
-// JAC = 2: z is passed as its bfloat16 copy (bf16_t[n][W]).
+// JAC = 2: z is passed as its bfloat16 copy (bf16_t[n][W]); JAC = 3: as
+// its FP8 copy with per-row-slice scales.
 // x (nullable, depth one): the previous iteration's x += alpha p_old is
 // applied here, where p_old is read anyway, instead of in the update kernel.
 template <typename T, int W, int JAC, int SPLIT>
@@ -383,6 +454,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
   const T* w = static_cast<const T*>(L.w);
   const T* deg = static_cast<const T*>(L.deg);
   const T* sd = static_cast<const T*>(L.sd);
+  const f8_t* z8 = reinterpret_cast<const f8_t*>(z);
+  const float* zsc = reinterpret_cast<const float*>(z8 + f8_scale_off(L.n, W));
   const bool xf = x && !first;
   T beta[V], alpha[V];
   double acc[V];
@@ -401,6 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
     for (int i = 0; i < V; ++i) nb[i] = 0;
     if (u < L.n)
       gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT, [&](int v) {
+        if constexpr (JAC == 3)
+          return ld_f8<T, V>(z8 + (size_t)v * W + c0, zsc[(size_t)v * Shape<W>::NS + slice]);
         if constexpr (JAC == 2)
           return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(z) + (size_t)v * W + c0);
         Vec<T, V> zv = ld<T, V>(z + (size_t)v * W + c0);
@@ -416,7 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
       add_heavy<T, W>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
       Vec<T, V> zu;
-      if constexpr (JAC == 2)
+      if constexpr (JAC == 3)
+        zu = ld_f8<T, V>(z8 + o, zsc[(size_t)u * Shape<W>::NS + slice]);
+      else if constexpr (JAC == 2)
         zu = ld_bf<T, V>(reinterpret_cast<const bf16_t*>(z) + o);
       else
         zu = ld<T, V>(z + o);
@@ -616,11 +693,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
 // ---------------------------------------------------------------------------
 // Smoother-only "solve" on the deepest level a truncated V-cycle uses:
 // x = S b (one Jacobi step from zero, S = omega D^-1); partial b.x if part.
-// BF: x is stored as bfloat16 (bf16_t[n][W]) and the partial uses the
-// rounded values.
-template <typename T, int W, bool DOT, bool BF>
+// ZF = 1: x is stored as bfloat16 (bf16_t[n][W]), ZF = 2: as FP8 with
+// per-row-slice scales; the partial uses the rounded values.
+template <typename T, int W, bool DOT, int ZF>
 __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restrict__ b,
                                                    void* __restrict__ xv, double* __restrict__ part) {
+  constexpr bool BF = ZF == 1;
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   __shared__ double lds[DOT ? RG * WS : 1];
   int slice, rb, grb;
@@ -647,11 +725,18 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
         xh.v[i] = f2bf(float(xo.v[i]));
         xo.v[i] = T(bf2f(xh.v[i]));
       }
-      if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
     }
+    if constexpr (ZF == 2) {
+      f8_t* x8 = static_cast<f8_t*>(xv);
+      st_f8<T, W>(xo, x8 + o, reinterpret_cast<float*>(x8 + f8_scale_off(L.n, W)) +
+                                  (size_t)u * Shape<W>::NS + slice);
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (DOT) acc[i] += double(bu.v[i]) * double(xo.v[i]);
     if constexpr (BF)
       st<bf16_t, V>(static_cast<bf16_t*>(xv) + o, xh);
-    else if (xv)
+    else if (ZF == 0 && xv)
       st<T, V>(static_cast<T*>(xv) + o, xo);
   }
   if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
@@ -659,11 +744,12 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
 
 // Jacobi-preconditioned CG update on level 0 (a V-cycle of depth one):
 // r_out = r_in - alpha q, x = (first ? 0 : x) + alpha p, z = S r_out;
-// partials |r_out|^2, sum x, r_out . z.  BF: z is stored (non-null) as
-// bfloat16 and r_out . z uses the rounded z.  xf: x is updated by the
+// partials |r_out|^2, sum x, r_out . z.  ZF = 1: z is stored (non-null) as
+// bfloat16, ZF = 2: as FP8 with per-row-slice scales; r_out . z uses the
+// rounded z.  xf: x is updated by the
 // product kernel of the next iteration instead (this kernel reads neither x
 // nor p, writes x = 0 on the first iteration and no sum-x partials).
-template <typename T, int W, bool BF>
+template <typename T, int W, int ZF>
 __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* __restrict__ r_in,
                                                           const T* __restrict__ q, const T* __restrict__ p,
                                                           T* __restrict__ x, T* __restrict__ r_out,
@@ -672,6 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
                                                           double* __restrict__ part_cs,
                                                           double* __restrict__ part_rz, int xf) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  constexpr bool BF = ZF == 1;
   __shared__ double lds[RG * WS];
   int slice, rb, grb;
   slice_of_block<W>(slice, rb, grb);
@@ -711,6 +798,14 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
         zh.v[i] = f2bf(float(zu.v[i]));
         zu.v[i] = T(bf2f(zh.v[i]));
       }
+    }
+    if constexpr (ZF == 2) {
+      f8_t* z8 = static_cast<f8_t*>(z);
+      st_f8<T, W>(zu, z8 + o, reinterpret_cast<float*>(z8 + f8_scale_off(L.n, W)) +
+                                  (size_t)u * Shape<W>::NS + slice);
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
       rr[i] += double(rn.v[i]) * double(rn.v[i]);
       cs[i] += double(xu.v[i]);
       rz[i] += double(rn.v[i]) * double(zu.v[i]);
@@ -719,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     st_nt<T, V>(r_out + o, rn);
     if constexpr (BF)
       st<bf16_t, V>(static_cast<bf16_t*>(z) + o, zh);
-    else if (z)
+    else if (ZF == 0 && z)
       st<T, V>(static_cast<T*>(z) + o, zu);
   }
   block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
@@ -1393,7 +1488,10 @@ struct Launch {
   static void spmm_pq(const LevelArgs& L, const void* z, void* p, void* q, void* x,
                       const double* scal, int first, double* part, int jac, hipStream_t s) {
 #define ARGS L, (const T*)z, (T*)p, (T*)q, (T*)x, scal, first, part
-    if (jac == 2) {
+    if (jac == 3) {
+      heavy<HK_F8>(L, z, nullptr, nullptr, scal, s);
+      CFC_LAUNCH(k_spmm_pq, L.n, T, W, 3);
+    } else if (jac == 2) {
       heavy<HK_BF16>(L, z, nullptr, nullptr, scal, s);
       CFC_LAUNCH(k_spmm_pq, L.n, T, W, 2);
     } else if (jac) {
@@ -1437,32 +1535,37 @@ struct Launch {
       CFC_LAUNCH(k_prolong_smooth, L.n, T, W, false);
 #undef ARGS
   }
-  static void jacobi(const LevelArgs& L, const void* b, void* x, double* part, int bf, hipStream_t s) {
+  static void jacobi(const LevelArgs& L, const void* b, void* x, double* part, int zf, hipStream_t s) {
     const int g = grid_units(L.n, RG);
     if (!g) return;
-    if (bf && part)
-      hipLaunchKernelGGL((k_jacobi<T, W, true, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
+    if (zf == 2 && part)
+      hipLaunchKernelGGL((k_jacobi<T, W, true, 2>), dim3(g * NS), dim3(kBlock), 0, s, L,
+                         (const T*)b, x, part);
+    else if (zf && part)
+      hipLaunchKernelGGL((k_jacobi<T, W, true, 1>), dim3(g * NS), dim3(kBlock), 0, s, L,
                          (const T*)b, x, part);
     else if (part)
-      hipLaunchKernelGGL((k_jacobi<T, W, true, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+      hipLaunchKernelGGL((k_jacobi<T, W, true, 0>), dim3(g * NS), dim3(kBlock), 0, s, L,
                          (const T*)b, x, part);
     else
-      hipLaunchKernelGGL((k_jacobi<T, W, false, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
+      hipLaunchKernelGGL((k_jacobi<T, W, false, 0>), dim3(g * NS), dim3(kBlock), 0, s, L,
                          (const T*)b, x, part);
   }
   static void update_jacobi(const LevelArgs& L, const void* r_in, const void* q, const void* p,
                             void* x, void* r_out, void* z, const double* scal, int first,
-                            double* prr, double* pcs, double* prz, int bf, int xf, hipStream_t s) {
+                            double* prr, double* pcs, double* prz, int zf, int xf, hipStream_t s) {
     const int g = grid_units(L.n, RG);
     if (!g) return;
-    if (bf)
-      hipLaunchKernelGGL((k_update_jacobi<T, W, true>), dim3(g * NS), dim3(kBlock), 0, s, L,
-                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first,
-                         prr, pcs, prz, xf);
+#define UJ(ZF)                                                                                       \
+  hipLaunchKernelGGL((k_update_jacobi<T, W, ZF>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r_in, \
+                     (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first, prr, pcs, prz, xf)
+    if (zf == 2)
+      UJ(2);
+    else if (zf)
+      UJ(1);
     else
-      hipLaunchKernelGGL((k_update_jacobi<T, W, false>), dim3(g * NS), dim3(kBlock), 0, s, L,
-                         (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first,
-                         prr, pcs, prz, xf);
+      UJ(0);
+#undef UJ
   }
   static void xfinal(int n, void* x, const void* p, const double* scal, double* pcs, hipStream_t s) {
     const int g = grid_units(n, RG);

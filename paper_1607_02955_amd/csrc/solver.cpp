@@ -365,16 +365,16 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       prof_begin(K_RESTRICT0);
       k.update_jacobi(lb, r_in, w.q.p, w.p.p, w.x.p, r_out, bfz ? w.z.p : nullptr,
                       w.scal.as<double>(), first_x, w.part_ptr(P_RR), w.part_ptr(P_CS),
-                      w.part_ptr(P_RZ), bfz ? 1 : 0, xfu ? 1 : 0, s);
-      const double ub = db.n * nw * upd_blocks(first_x) + 2.0 * es * db.n + (bfz ? 2.0 * db.n * w.W : 0.0);
+                      w.part_ptr(P_RZ), zfmt(), xfu ? 1 : 0, s);
+      const double ub = db.n * nw * upd_blocks(first_x) + 2.0 * es * db.n + (bfz ? zbytes() * db.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
       g_rr = grid_for(db.n, k.rg);
       g_cs = xfu ? 0 : g_rr;  // with xfu the sums of x come with the last update
     } else {
       // r . S r (and the bfloat16 copy of z = S r when the product gathers it)
-      k.jacobi(lb, r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), bfz ? 1 : 0, s);
-      bytes += db.n * nw + es * db.n + (bfz ? 2.0 * db.n * w.W : 0.0);
+      k.jacobi(lb, r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), zfmt(), s);
+      bytes += db.n * nw + es * db.n + (bfz ? zbytes() * db.n * w.W : 0.0);
     }
     g_rz = grid_for(db.n, k.rg);
     return;
@@ -565,8 +565,8 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
   // one Jacobi step as the whole preconditioner (no exact solve on level 0)
   const bool jac = jac_top;
   k.spmm_pq(w.la[base], jac && !bfz ? r_in : w.z.p, w.p.p, w.q.p, xfu ? w.x.p : nullptr,
-            w.scal.as<double>(), first, w.part_ptr(P_PQ), bfz ? 2 : (jac ? 1 : 0), stream);
-  const double sb = (bfz ? d0.n * (double)W * (2.0 + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
+            w.scal.as<double>(), first, w.part_ptr(P_PQ), bfz ? (zf8 ? 3 : 2) : (jac ? 1 : 0), stream);
+  const double sb = (bfz ? d0.n * (double)W * (zbytes() + es * (first ? 2 : 4)) + mat_bytes(d0, !d0.unit, es)
                          : d0.n * nw * (first ? 3 : 5) + mat_bytes(d0, !d0.unit, es) +
                                (jac ? es * d0.n : 0.0)) +
                     (xfu && !first ? 2.0 * d0.n * nw : 0.0);
@@ -836,6 +836,13 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   base = schur ? 1 : 0;
   jac_top = nuse - base == 1 && smoothed;
   bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
+  // FP8 z (one scale per row and column slice) when the preconditioner is
+  // one Jacobi step on the level the CG runs on, on request (CFC_Z_FP8=1):
+  // the gathered slice row is half as wide but costs a second load for its
+  // scale, and R-MAT-20's operator product measured 2.69 ms against 2.39 ms
+  // with bfloat16 (BA-100k 250 against 257 us)
+  const char* z8 = std::getenv("CFC_Z_FP8");
+  zf8 = bfz && jac_top && ws->W >= 32 && z8 && z8[0] == '1';
   // The product kernel carries the x updates (CFC_FUSE_X=0 keeps them in
   // the update kernel).
   const char* fx = std::getenv("CFC_FUSE_X");
@@ -873,6 +880,7 @@ void Solver::finish(cfc_solve_stats* st) {
   st->block_width = ws->W;
   st->precision = params.precision;
   st->levels_used = nuse;
+  st->z_format = zfmt();
   st->max_rel_residual = std::max(st->max_rel_residual, max_rel);
   st->solve_ms += ms;
   st->model_bytes += bytes;

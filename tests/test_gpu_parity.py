@@ -446,9 +446,9 @@ def test_schur_cg_matches_level0_cg(ctx, W, monkeypatch):
 
 @pytest.mark.parametrize("case", ["depth1_hubs", "elim_depth2"])
 def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
-    """The bfloat16 copy of z = M^-1 r (depth one, or elimination plus one
-    Jacobi step) gives the oracle's resistances at the requested tolerance,
-    as the FP32 z does, in about as many iterations."""
+    """The bfloat16 and the FP8 copies of z = M^-1 r (depth one, or
+    elimination plus one Jacobi step) give the oracle's resistances at the
+    requested tolerance, as the FP32 z does, in about as many iterations."""
     if case == "depth1_hubs":
         eg = synth.barabasi_albert(3000, 3, seed=44)  # hubs above the heavy-row threshold
         g = load(ctx, eg, coarsest_max=64)
@@ -463,19 +463,23 @@ def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
     s = rng.integers(0, eg.n, 2 * W + 3)
     t = rng.integers(0, eg.n, 2 * W + 3)
     its, res = {}, {}
-    # (bfloat16 z, x updates in the product kernel): both off, z only, both on
-    for bz, fx in (("0", "0"), ("1", "0"), ("1", "1")):
+    # (compressed z, FP8 rather than bfloat16, x updates in the product
+    # kernel): FP32 z; bfloat16 z; FP8 z; FP8 z with fused x updates
+    for bz, z8, fx, zf in (("0", "0", "0", 0), ("1", "0", "0", 1), ("1", "1", "0", 2), ("1", "1", "1", 2)):
         monkeypatch.setenv("CFC_BF16_Z", bz)
+        monkeypatch.setenv("CFC_Z_FP8", z8)
         monkeypatch.setenv("CFC_FUSE_X", fx)
         r, st = g.resistance(s, t, block=W, tol=1e-8, levels=depth, stats=True, max_inner=3000)
-        say("bf16 z", case, bz, "fused x", fx, st["inner_iters"], st["refine_steps"])
+        say("z format", case, st["z_format"], "fused x", fx, st["inner_iters"], st["refine_steps"])
+        assert st["z_format"] == zf
         np.testing.assert_allclose(r, Rm[s, t], rtol=1e-7, atol=1e-12)
-        its[bz + fx], res[bz + fx] = st["inner_iters"], r
-    assert its["10"] <= 1.1 * its["00"] + 3
+        its[bz + z8 + fx], res[bz + z8 + fx] = st["inner_iters"], r
+    assert its["100"] <= 1.1 * its["000"] + 3
+    assert its["110"] <= 1.1 * its["000"] + 3
     # carrying x in the product kernel is the same arithmetic (only the
     # order of the column sums of x may differ)
-    assert its["11"] == its["10"]
-    np.testing.assert_allclose(res["11"], res["10"], rtol=1e-12, atol=1e-15)
+    assert its["111"] == its["110"]
+    np.testing.assert_allclose(res["111"], res["110"], rtol=1e-12, atol=1e-15)
 
 
 def test_elimination_to_two_nodes_is_exact(ctx):
