@@ -81,9 +81,13 @@ def make_workload(name):
         g = synth.grid(32)
         return g, dict(kind="exact", block=256, tol=1e-10, queries=1, precision=1, nodes=[0])
     if name == "rmat20_sampling":
-        # one step = 4 of the 64 query nodes x 1000 pivots
+        # one step = 4 of the 64 query nodes x 1000 pivots; eager launches
+        # (each operator product takes ~2.4 ms, so graph replay gains nothing:
+        # 6,312 RHS/s eager against 6,278 replayed) keep every launch of the
+        # timed region under the HIP events that the roofline uses
         g = synth.cached("rmat20", synth.rmat, 20, 16, seed=1)
-        return g, dict(kind="sampling", k=1000, block=256, tol=1e-6, queries=64, per_step=4)
+        return g, dict(kind="sampling", k=1000, block=256, tol=1e-6, queries=64, per_step=4,
+                       use_graph=0)
     if name == "road2048_jl256":
         g = synth.cached("road2048", synth.road_grid, 2048, seed=1)
         return g, dict(kind="jl", k=256, block=0, tol=1e-6, queries=32)
@@ -365,6 +369,8 @@ def main():
                     help="largest degree of an eliminated node (0 = the library default)")
     ap.add_argument("--nest", type=int, default=0,
                     help="aggregation levels the numbering nests (0 = auto, 1 = all, 2 = kept)")
+    ap.add_argument("--max-complexity", type=float, default=0.0,
+                    help="hierarchy complexity budget (0 = the library default, -1 = none)")
     ap.add_argument("--block", type=int, default=-1, help="block width W (default: the workload's)")
     ap.add_argument("--use-graph", type=int, default=-1,
                     help="replay PCG iterations from HIP graphs (1/0; default: on)")
@@ -472,13 +478,14 @@ def measure(workload, args, extras=True, ctx=None):
     g = cfc.Graph.from_edgelist(ctx, eg)
     t0 = time.perf_counter()
     g.build_hierarchy(eliminate=args.eliminate, order=args.order, elim_degree=args.elim_degree,
-                      nest=args.nest)
+                      nest=args.nest, max_complexity=args.max_complexity)
     setup_s = time.perf_counter() - t0
     info = g.info()
     progress(f"hierarchy: {info['levels']} levels, {info['eliminated']} eliminated, {setup_s:.1f} s")
     prec = spec.get("precision", 0)
     # PCG iterations are replayed from HIP graphs (one per iteration; BA-100k
-    # +1.3%, R-MAT-20 +0.3%, 32^2 grid +5.5% against eager launches)
+    # +1.3%, 32^2 grid +5.5% against eager launches) unless the workload says
+    # otherwise; replayed launches carry no HIP events
     use_graph = args.use_graph if args.use_graph >= 0 else spec.get("use_graph", 1)
     if args.block >= 0:
         spec["block"] = args.block
