@@ -81,12 +81,14 @@ def make_workload(name):
         g = synth.grid(32)
         return g, dict(kind="exact", block=256, tol=1e-10, queries=1, precision=1, nodes=[0])
     if name == "rmat20_sampling":
-        # one step = 4 of the 64 query nodes x 1000 pivots; eager launches
-        # (each operator product takes ~2.4 ms, so graph replay gains nothing:
-        # 6,312 RHS/s eager against 6,278 replayed) keep every launch of the
+        # one step = 4 of the 64 query nodes x 1000 pivots, in blocks of 512
+        # (6,917 RHS/s against 6,290 at 256 and 4,644 at 128: a gathered
+        # neighbour row serves twice the columns); eager launches (an operator
+        # product takes milliseconds, so graph replay gains nothing: 6,312
+        # RHS/s eager against 6,278 replayed at 256) keep every launch of the
         # timed region under the HIP events that the roofline uses
         g = synth.cached("rmat20", synth.rmat, 20, 16, seed=1)
-        return g, dict(kind="sampling", k=1000, block=256, tol=1e-6, queries=64, per_step=4,
+        return g, dict(kind="sampling", k=1000, block=512, tol=1e-6, queries=64, per_step=4,
                        use_graph=0)
     if name == "road2048_jl256":
         g = synth.cached("road2048", synth.road_grid, 2048, seed=1)
