@@ -15,8 +15,8 @@ constexpr int kElimDeg = 4;      // neighbour slots of an eliminated row
 __host__ __device__ constexpr int slices_of(int W) {
   return W >= 512 ? 8 : (W >= 256 ? 4 : (W >= 32 ? W / 32 : 1));
 }
-// Byte offset of the per-row-slice scales (float[n][slices_of(W)]) after the
-// n x W bytes of an FP8 copy of z.
+// Byte offset of the per-row-slice scales (float[n][KernTable::ns8]) after
+// the n x W bytes of an FP8 copy of z.
 __host__ __device__ constexpr size_t f8_scale_off(int n, int W) {
   return ((size_t)n * (size_t)W + 255) & ~size_t(255);
 }
@@ -84,6 +84,13 @@ struct KernTable {
   // workgroups per column slice (= rows of partial sums) of a kernel over
   // `units` units of the level
   int (*rows_grid)(const LevelArgs&, int units);
+  // The FP8 paths (spmm_pq jac = 3, jacobi / update_jacobi zf = 2) slice
+  // the columns ns8 ways (half the regular count) with rg8 row groups per
+  // workgroup: their partial sums have rows_grid8 / grid_for(units, rg8)
+  // rows, and the scales of an FP8 z are float[n][ns8].
+  int rg8 = 0;
+  int ns8 = 0;
+  int (*rows_grid8)(const LevelArgs&, int units);
   // PCG step: q = L z + beta q, p = z + beta p (first: beta = 0); partial p.q.
   // jac = 1: z is passed as r and formed as S r on the fly; jac = 2: z is
   // its bfloat16 copy (uint16[n][W]); jac = 3: its FP8 copy (uint8[n][W],

@@ -30,14 +30,14 @@ namespace cfc {
 namespace dev {
 
 // Column slicing and lane shape of a W-wide block.
-template <int W> struct Shape {
+template <int W, int NSX = slices_of(W)> struct Shape {
   // column slices: at most one per XCD, 32 columns wide up to W = 128 (a
   // slice row of >= 128 B in FP32 fills whole cache lines) and 64 columns
   // from W = 256, so that the bfloat16 rows the operator product gathers
   // are 128 B too: on R-MAT-20 at W = 256, 4 slices of 64 columns measured
   // 3.05 ms per product against 3.98 ms for 8 slices of 32 (random 64-byte
   // reads use HBM worse than 128-byte ones)
-  static constexpr int NS = slices_of(W);
+  static constexpr int NS = NSX;
   static constexpr int WS = W / NS;           // columns per slice
   static constexpr int V = WS >= 4 ? 4 : 1;   // columns per lane
   static constexpr int LPR = WS / V;          // lanes per row group
@@ -48,9 +48,9 @@ template <int W> struct Shape {
 // slice.  Workgroup b runs on XCD b mod 8; the 8/NS XCDs that share a slice
 // each take a contiguous part of the row range (rb blocks in order), so a
 // row's neighbours are most often in the same XCD's L2.
-template <int W>
+template <int W, int NSX = slices_of(W)>
 __device__ __forceinline__ void slice_of_block(int& slice, int& rb, int& grb) {
-  constexpr int NS = Shape<W>::NS;
+  constexpr int NS = Shape<W, NSX>::NS;
   constexpr int XPS = 8 / NS;  // XCDs per slice
   const int b = blockIdx.x;
   slice = b % NS;
@@ -102,8 +102,9 @@ __device__ __forceinline__ Vec<T, V> ld_bf(const bf16_t* p) {
 // row's column slice (the LPR lanes of one row group) shares one FP32 scale
 // max|z| / 448, stored after the n x W bytes (float[n][NS] at
 // f8_scale_off(n, W)).  As with bfloat16, z is rounded once where it is
-// formed and every later use sees the dequantised value; a gathered slice
-// row is WS bytes plus its scale.
+// formed and every later use sees the dequantised value.  The kernels that
+// write or gather it run with half the regular number of column slices
+// (NSX = NS / 2), so a gathered slice row is 128 bytes plus its scale.
 typedef unsigned char f8_t;
 constexpr float kF8Max = 448.0f;
 
@@ -130,9 +131,9 @@ __device__ __forceinline__ Vec<T, V> ld_f8(const f8_t* p, float scale) {
 // stored as zeros); values are clamped to +-448 (NaN stays NaN) and z is
 // replaced by the dequantised values.  Lane 0 of the row group stores the
 // scale.
-template <typename T, int W>
-__device__ __forceinline__ void st_f8(Vec<T, Shape<W>::V>& z, f8_t* dst, float* sc_dst) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V;
+template <typename T, int W, int NSX = slices_of(W)>
+__device__ __forceinline__ void st_f8(Vec<T, Shape<W, NSX>::V>& z, f8_t* dst, float* sc_dst) {
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V;
   float m = 0.0f;
 #pragma unroll
   for (int i = 0; i < V; ++i) {
@@ -204,9 +205,10 @@ __device__ __forceinline__ void block_tiles(int ntiles, int rb, int G, int& tb, 
 
 // Sum acc over the row groups of the workgroup and store the WS slice
 // columns to out (which points at the slice's first column).
-template <int W>
+template <int W, int NSX = slices_of(W)>
 __device__ __forceinline__ void block_store(const double* acc, double* lds, double* out) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, RG = Shape<W, NSX>::RG,
+                WS = Shape<W, NSX>::WS;
   const int rg = threadIdx.x / LPR, c0 = (threadIdx.x % LPR) * V;
 #pragma unroll
   for (int i = 0; i < V; ++i) lds[rg * WS + c0 + i] = acc[i];
@@ -232,10 +234,10 @@ __device__ __forceinline__ T wt(const T* w, int e) {
 #endif
 constexpr int kGatherDepth = CFC_GATHER_DEPTH;
 
-template <typename T, int W, class F>
+template <typename T, int W, int NSX = slices_of(W), class F>
 __device__ __forceinline__ void gather_acc(T* nb, const int* __restrict__ col, const T* __restrict__ w,
                                            int e0, int e1, int s, int S, F&& f) {
-  constexpr int V = Shape<W>::V, D = kGatherDepth;
+  constexpr int V = Shape<W, NSX>::V, D = kGatherDepth;
   int e = e0 + s;
   for (; e + (D - 1) * S < e1; e += D * S) {
     int v[D];
@@ -266,18 +268,18 @@ __device__ __forceinline__ void gather_acc(T* nb, const int* __restrict__ col, c
 // each taking every SPLIT-th edge; a tile holds RG / SPLIT units.  After the
 // gathers, wg_combine hands each unit's leading row group (split 0) the sum
 // over its SPLIT groups, in a fixed order.
-template <int W, int SPLIT>
+template <int W, int SPLIT, int NSX = slices_of(W)>
 struct Deco {
-  static_assert(Shape<W>::RG % SPLIT == 0, "split must divide the row groups");
-  static constexpr int PER_TILE = Shape<W>::RG / SPLIT;
+  static_assert(Shape<W, NSX>::RG % SPLIT == 0, "split must divide the row groups");
+  static constexpr int PER_TILE = Shape<W, NSX>::RG / SPLIT;
   __device__ static int unit(int t, int rg) { return t * PER_TILE + rg / SPLIT; }
   __device__ static int split(int rg) { return rg % SPLIT; }
   __device__ static bool leader(int rg) { return rg % SPLIT == 0; }
 };
 
-template <typename T, int W, int SPLIT>
+template <typename T, int W, int SPLIT, int NSX = slices_of(W)>
 __device__ __forceinline__ void wg_combine(T* nb, T* lds) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, WS = Shape<W>::WS;
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, WS = Shape<W, NSX>::WS;
   const int rg = threadIdx.x / LPR, c = (threadIdx.x % LPR) * V;
 #pragma unroll
   for (int i = 0; i < V; ++i) lds[rg * WS + c + i] = nb[i];
@@ -294,12 +296,12 @@ __device__ __forceinline__ void wg_combine(T* nb, T* lds) {
 }
 
 // nb += the segment partials of heavy row u (fixed order); no-op for a light row.
-template <typename T, int W>
+template <typename T, int W, int NSX = slices_of(W)>
 __device__ __forceinline__ void add_heavy(const LevelArgs& L, int u, T* nb, int c0) {
   if (!L.heavy) return;
   const int h = L.heavy[u];
   if (h < 0) return;
-  constexpr int V = Shape<W>::V;
+  constexpr int V = Shape<W, NSX>::V;
   if (L.hsum) {
     const Vec<T, V> x = ld<T, V>(static_cast<const T*>(L.hsum) + (size_t)h * W + c0);
 #pragma unroll
@@ -323,14 +325,14 @@ enum HeavyKind {
   HK_F8 = 7      // the gathered block is FP8 with per-row-slice scales
 };
 
-template <typename T, int W, int KIND>
+template <typename T, int W, int KIND, int NSX = slices_of(W)>
 __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restrict__ a,
                                                   const T* __restrict__ q, const T* __restrict__ xc,
                                                   const double* __restrict__ scal) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, RG = Shape<W, NSX>::RG, WS = Shape<W, NSX>::WS;
   __shared__ T ldc[RG * WS];
   int slice, sgi, nsg;
-  slice_of_block<W>(slice, sgi, nsg);
+  slice_of_block<W, NSX>(slice, sgi, nsg);
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* w = static_cast<const T*>(L.hw);
   const T* sd = static_cast<const T*>(L.sd);
@@ -345,10 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
     T nb[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) nb[i] = 0;
-    gather_acc<T, W>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
+    gather_acc<T, W, NSX>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
       if constexpr (KIND == HK_F8)
         return ld_f8<T, V>(reinterpret_cast<const f8_t*>(a) + (size_t)v * W + c0,
-                           zsc[(size_t)v * Shape<W>::NS + slice]);
+                           zsc[(size_t)v * Shape<W, NSX>::NS + slice]);
       if constexpr (KIND == HK_BF16)
         return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(a) + (size_t)v * W + c0);
       if constexpr (KIND == HK_RES32) {
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
       }
       return r;
     });
-    wg_combine<T, W, RG>(nb, ldc);
+    wg_combine<T, W, RG, NSX>(nb, ldc);
     if (rg == 0) {
       Vec<T, V> o;
 #pragma unroll
@@ -438,18 +440,18 @@ __global__ __launch_bounds__(kBlock) void k_heavy_sum(LevelArgs L) {
 // its FP8 copy with per-row-slice scales.
 // x (nullable, depth one): the previous iteration's x += alpha p_old is
 // applied here, where p_old is read anyway, instead of in the update kernel.
-template <typename T, int W, int JAC, int SPLIT>
+template <typename T, int W, int JAC, int SPLIT, int NSX = slices_of(W)>
 __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __restrict__ z,
                                                     T* __restrict__ p, T* __restrict__ q,
                                                     T* __restrict__ x,
                                                     const double* __restrict__ scal, int first,
                                                     double* __restrict__ part) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
-  using D = Deco<W, SPLIT>;
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, RG = Shape<W, NSX>::RG, WS = Shape<W, NSX>::WS;
+  using D = Deco<W, SPLIT, NSX>;
   __shared__ double lds[RG * WS];
   __shared__ T ldc[SPLIT > 1 ? RG * WS : 1];
   int slice, rb, grb;
-  slice_of_block<W>(slice, rb, grb);
+  slice_of_block<W, NSX>(slice, rb, grb);
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* w = static_cast<const T*>(L.w);
   const T* deg = static_cast<const T*>(L.deg);
@@ -473,9 +475,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
 #pragma unroll
     for (int i = 0; i < V; ++i) nb[i] = 0;
     if (u < L.n)
-      gather_acc<T, W>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT, [&](int v) {
+      gather_acc<T, W, NSX>(nb, L.col, w, L.rowptr[u], L.rowptr[u + 1], D::split(rg), SPLIT, [&](int v) {
         if constexpr (JAC == 3)
-          return ld_f8<T, V>(z8 + (size_t)v * W + c0, zsc[(size_t)v * Shape<W>::NS + slice]);
+          return ld_f8<T, V>(z8 + (size_t)v * W + c0, zsc[(size_t)v * Shape<W, NSX>::NS + slice]);
         if constexpr (JAC == 2)
           return ld_bf<T, V>(reinterpret_cast<const bf16_t*>(z) + (size_t)v * W + c0);
         Vec<T, V> zv = ld<T, V>(z + (size_t)v * W + c0);
@@ -486,13 +488,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
         }
         return zv;
       });
-    if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT>(nb, ldc);
+    if constexpr (SPLIT > 1) wg_combine<T, W, SPLIT, NSX>(nb, ldc);
     if (u < L.n && D::leader(rg)) {
-      add_heavy<T, W>(L, u, nb, c0);
+      add_heavy<T, W, NSX>(L, u, nb, c0);
       const size_t o = (size_t)u * W + c0;
       Vec<T, V> zu;
       if constexpr (JAC == 3)
-        zu = ld_f8<T, V>(z8 + o, zsc[(size_t)u * Shape<W>::NS + slice]);
+        zu = ld_f8<T, V>(z8 + o, zsc[(size_t)u * Shape<W, NSX>::NS + slice]);
       else if constexpr (JAC == 2)
         zu = ld_bf<T, V>(reinterpret_cast<const bf16_t*>(z) + o);
       else
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pq(LevelArgs L, const T* __rest
       for (int i = 0; i < V; ++i) acc[i] += double(pn.v[i]) * double(qn.v[i]);
     }
   }
-  block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+  block_store<W, NSX>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // ---------------------------------------------------------------------------
@@ -695,14 +697,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong_smooth(LevelArgs L, const T*
 // x = S b (one Jacobi step from zero, S = omega D^-1); partial b.x if part.
 // ZF = 1: x is stored as bfloat16 (bf16_t[n][W]), ZF = 2: as FP8 with
 // per-row-slice scales; the partial uses the rounded values.
-template <typename T, int W, bool DOT, int ZF>
+template <typename T, int W, bool DOT, int ZF, int NSX = slices_of(W)>
 __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restrict__ b,
                                                    void* __restrict__ xv, double* __restrict__ part) {
   constexpr bool BF = ZF == 1;
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, RG = Shape<W, NSX>::RG, WS = Shape<W, NSX>::WS;
   __shared__ double lds[DOT ? RG * WS : 1];
   int slice, rb, grb;
-  slice_of_block<W>(slice, rb, grb);
+  slice_of_block<W, NSX>(slice, rb, grb);
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* sd = static_cast<const T*>(L.sd);
   double acc[V];
@@ -728,8 +730,8 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
     }
     if constexpr (ZF == 2) {
       f8_t* x8 = static_cast<f8_t*>(xv);
-      st_f8<T, W>(xo, x8 + o, reinterpret_cast<float*>(x8 + f8_scale_off(L.n, W)) +
-                                  (size_t)u * Shape<W>::NS + slice);
+      st_f8<T, W, NSX>(xo, x8 + o, reinterpret_cast<float*>(x8 + f8_scale_off(L.n, W)) +
+                                  (size_t)u * Shape<W, NSX>::NS + slice);
     }
 #pragma unroll
     for (int i = 0; i < V; ++i)
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
     else if (ZF == 0 && xv)
       st<T, V>(static_cast<T*>(xv) + o, xo);
   }
-  if (DOT) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+  if (DOT) block_store<W, NSX>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // Jacobi-preconditioned CG update on level 0 (a V-cycle of depth one):
@@ -749,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelArgs L, const T* __restr
 // rounded z.  xf: x is updated by the
 // product kernel of the next iteration instead (this kernel reads neither x
 // nor p, writes x = 0 on the first iteration and no sum-x partials).
-template <typename T, int W, int ZF>
+template <typename T, int W, int ZF, int NSX = slices_of(W)>
 __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* __restrict__ r_in,
                                                           const T* __restrict__ q, const T* __restrict__ p,
                                                           T* __restrict__ x, T* __restrict__ r_out,
@@ -757,11 +759,11 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
                                                           int first, double* __restrict__ part_rr,
                                                           double* __restrict__ part_cs,
                                                           double* __restrict__ part_rz, int xf) {
-  constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
+  constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, RG = Shape<W, NSX>::RG, WS = Shape<W, NSX>::WS;
   constexpr bool BF = ZF == 1;
   __shared__ double lds[RG * WS];
   int slice, rb, grb;
-  slice_of_block<W>(slice, rb, grb);
+  slice_of_block<W, NSX>(slice, rb, grb);
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
   const T* sd = static_cast<const T*>(L.sd);
   T alpha[V];
@@ -801,8 +803,8 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     }
     if constexpr (ZF == 2) {
       f8_t* z8 = static_cast<f8_t*>(z);
-      st_f8<T, W>(zu, z8 + o, reinterpret_cast<float*>(z8 + f8_scale_off(L.n, W)) +
-                                  (size_t)u * Shape<W>::NS + slice);
+      st_f8<T, W, NSX>(zu, z8 + o, reinterpret_cast<float*>(z8 + f8_scale_off(L.n, W)) +
+                                  (size_t)u * Shape<W, NSX>::NS + slice);
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
@@ -817,9 +819,9 @@ __global__ __launch_bounds__(kBlock) void k_update_jacobi(LevelArgs L, const T* 
     else if (ZF == 0 && z)
       st<T, V>(static_cast<T*>(z) + o, zu);
   }
-  block_store<W>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
-  if (!xf) block_store<W>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
-  block_store<W>(rz, lds, part_rz + (size_t)rb * W + slice * WS);
+  block_store<W, NSX>(rr, lds, part_rr + (size_t)rb * W + slice * WS);
+  if (!xf) block_store<W, NSX>(cs, lds, part_cs + (size_t)rb * W + slice * WS);
+  block_store<W, NSX>(rz, lds, part_rz + (size_t)rb * W + slice * WS);
 }
 
 // Last CG update of x when the product kernel carries the x updates:
@@ -1449,10 +1451,19 @@ template <typename T, int W>
 struct Launch {
   static constexpr int RG = Shape<W>::RG;
   static constexpr int NS = Shape<W>::NS;
+  // The kernels that write or gather z in FP8 use half as many column
+  // slices (128 columns from W = 256), so that a gathered FP8 slice row is
+  // 128 bytes, as a bfloat16 one is with the regular slicing.
+  static constexpr int NS8 = NS >= 2 ? NS / 2 : 1;
+  static constexpr int RG8 = Shape<W, NS8>::RG;
 
   // workgroups per slice for a kernel over `units` units of level L
   static int rows_grid(const LevelArgs& L, int units) {
     return grid_for(units, RG / std::min(std::max(L.split, 1), RG));
+  }
+  // the same for the FP8 product (row splits of at most 4)
+  static int rows_grid8(const LevelArgs& L, int units) {
+    return grid_for(units, RG8 / (L.split >= 4 ? 4 : 1));
   }
 
 #define CFC_LAUNCH(K, units, ...)                                                              \
@@ -1489,8 +1500,18 @@ struct Launch {
                       const double* scal, int first, double* part, int jac, hipStream_t s) {
 #define ARGS L, (const T*)z, (T*)p, (T*)q, (T*)x, scal, first, part
     if (jac == 3) {
-      heavy<HK_F8>(L, z, nullptr, nullptr, scal, s);
-      CFC_LAUNCH(k_spmm_pq, L.n, T, W, 3);
+      if (L.nseg) {
+        const int gh = std::min(L.nseg, 4 * kMaxGrid);
+        hipLaunchKernelGGL((k_heavy<T, W, HK_F8, NS8>), dim3(gh * NS8), dim3(kBlock), 0, s, L,
+                           (const T*)z, (const T*)nullptr, (const T*)nullptr, scal);
+        heavy_sum<T>(L, s);
+      }
+      const int g8 = rows_grid8(L, L.n);
+      if (!g8) return;
+      if (L.split >= 4)
+        hipLaunchKernelGGL((k_spmm_pq<T, W, 3, 4, NS8>), dim3(g8 * NS8), dim3(kBlock), 0, s, ARGS);
+      else
+        hipLaunchKernelGGL((k_spmm_pq<T, W, 3, 1, NS8>), dim3(g8 * NS8), dim3(kBlock), 0, s, ARGS);
     } else if (jac == 2) {
       heavy<HK_BF16>(L, z, nullptr, nullptr, scal, s);
       CFC_LAUNCH(k_spmm_pq, L.n, T, W, 2);
@@ -1539,8 +1560,8 @@ struct Launch {
     const int g = grid_units(L.n, RG);
     if (!g) return;
     if (zf == 2 && part)
-      hipLaunchKernelGGL((k_jacobi<T, W, true, 2>), dim3(g * NS), dim3(kBlock), 0, s, L,
-                         (const T*)b, x, part);
+      hipLaunchKernelGGL((k_jacobi<T, W, true, 2, NS8>), dim3(grid_units(L.n, RG8) * NS8), dim3(kBlock),
+                         0, s, L, (const T*)b, x, part);
     else if (zf && part)
       hipLaunchKernelGGL((k_jacobi<T, W, true, 1>), dim3(g * NS), dim3(kBlock), 0, s, L,
                          (const T*)b, x, part);
@@ -1560,7 +1581,9 @@ struct Launch {
   hipLaunchKernelGGL((k_update_jacobi<T, W, ZF>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r_in, \
                      (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first, prr, pcs, prz, xf)
     if (zf == 2)
-      UJ(2);
+      hipLaunchKernelGGL((k_update_jacobi<T, W, 2, NS8>), dim3(grid_units(L.n, RG8) * NS8), dim3(kBlock),
+                         0, s, L, (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal,
+                         first, prr, pcs, prz, xf);
     else if (zf)
       UJ(1);
     else
@@ -1697,6 +1720,9 @@ struct Launch {
     t.esize = sizeof(T);
     t.rg = RG;
     t.rows_grid = &rows_grid;
+    t.rg8 = RG8;
+    t.ns8 = NS8;
+    t.rows_grid8 = &rows_grid8;
     t.spmm_pq = &spmm_pq;
     t.update_restrict = &update_restrict;
     t.restrict_ = &restrict_;

@@ -369,14 +369,14 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       const double ub = db.n * nw * upd_blocks(first_x) + 2.0 * es * db.n + (bfz ? zbytes() * db.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
-      g_rr = grid_for(db.n, k.rg);
+      g_rr = grid_for(db.n, zf8 ? k.rg8 : k.rg);
       g_cs = xfu ? 0 : g_rr;  // with xfu the sums of x come with the last update
     } else {
       // r . S r (and the bfloat16 copy of z = S r when the product gathers it)
       k.jacobi(lb, r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), zfmt(), s);
       bytes += db.n * nw + es * db.n + (bfz ? zbytes() * db.n * w.W : 0.0);
     }
-    g_rz = grid_for(db.n, k.rg);
+    g_rz = grid_for(db.n, zf8 ? k.rg8 : k.rg);
     return;
   }
   if (!schur && d0.nC > 0 && L >= 2) {
@@ -572,8 +572,8 @@ void Solver::iteration(bool first, void* r_in, void* r_out) {
                     (xfu && !first ? 2.0 * d0.n * nw : 0.0);
   prof_end(K_SPMM, sb);
   bytes += sb;
-  finalize(W, F_ALPHA, k.rows_grid(w.la[base], d0.n), w.part_ptr(P_PQ), 0, nullptr, 0, nullptr,
-           w.scal.as<double>(), stream);
+  finalize(W, F_ALPHA, zf8 ? k.rows_grid8(w.la[base], d0.n) : k.rows_grid(w.la[base], d0.n),
+           w.part_ptr(P_PQ), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
   vcycle(true, first, r_in, r_out);
   finalize(W, F_BETA, g_rz, w.part_ptr(P_RZ), g_rr, w.part_ptr(P_RR), g_cs, w.part_ptr(P_CS),
            w.scal.as<double>(), stream, w.mirror_dev);
@@ -837,12 +837,13 @@ Solver::Solver(Graph& gr, const cfc_solve_params& p, hipStream_t so, Ctx* mem) :
   jac_top = nuse - base == 1 && smoothed;
   bfz = !ws->fp64 && (jac1 || elim2) && !(bz && bz[0] == '0');
   // FP8 z (one scale per row and column slice) when the preconditioner is
-  // one Jacobi step on the level the CG runs on, on request (CFC_Z_FP8=1):
-  // the gathered slice row is half as wide but costs a second load for its
-  // scale, and R-MAT-20's operator product measured 2.69 ms against 2.39 ms
-  // with bfloat16 (BA-100k 250 against 257 us)
+  // one Jacobi step on the level the CG runs on (CFC_Z_FP8=0 keeps
+  // bfloat16): with 128-column slices a gathered FP8 row is 128 bytes and
+  // serves twice the columns of a bfloat16 one; R-MAT-20's operator product
+  // at W = 512 measured 3.96 ms against 4.58 ms, BA-100k's 229 against
+  // 258 us, with the same iteration counts
   const char* z8 = std::getenv("CFC_Z_FP8");
-  zf8 = bfz && jac_top && ws->W >= 32 && z8 && z8[0] == '1';
+  zf8 = bfz && jac_top && ws->W >= 32 && !(z8 && z8[0] == '0');
   // The product kernel carries the x updates (CFC_FUSE_X=0 keeps them in
   // the update kernel).
   const char* fx = std::getenv("CFC_FUSE_X");

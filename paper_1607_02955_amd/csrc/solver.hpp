@@ -58,7 +58,7 @@ struct Solver {
   bool zf8 = false;  // ... or, when the preconditioner is one Jacobi step, as FP8
   int zfmt() const { return bfz ? (zf8 ? 2 : 1) : 0; }
   // bytes per value of the stored z (FP8 adds its per-row-slice scale)
-  double zbytes() const { return zf8 ? 1.0 + 4.0 * slices_of(ws->W) / ws->W : 2.0; }
+  double zbytes() const { return zf8 ? 1.0 + 4.0 * ws->kt->ns8 / ws->W : 2.0; }
   // Schur mode (level 0 an elimination level, depth two or more): the inner
   // CG runs on level 1, the Schur complement S, preconditioned by one
   // Jacobi step (depth two) or by the V-cycle from level 1; pcg() folds the
