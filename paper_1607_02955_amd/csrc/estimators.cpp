@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -74,26 +75,64 @@ static double tune_score(Graph& g, const cfc_solve_params& p0, int W, int depth)
   p.block = W;
   p.levels = depth;
   p.max_refine = 1;
-  p.max_inner = 100;
+  p.max_inner = 200;
   p.check_every = 4;
-  p.inner_tol = 1e-3;
-  p.tol = 1e-300;
-  std::vector<int64_t> s(W), t(W);
+  // the reduction the real solves ask of an inner solve: 1e-4 for FP32 (the
+  // floor of the first of two refinement steps, with no outer tolerance to
+  // stop at), the tolerance itself (at least 1e-8) for FP64, whose inner
+  // solves aim at the outer tolerance.  A cheaper target favours the
+  // shallow cycles, whose early iterations converge fastest (32^2 grid,
+  // FP64 to 1e-10: aiming at 1e-3 picked depth 2, 104,138 RHS/s, over the
+  // full depth, 175,864), and the FP64 target must not be 0: it would run
+  // every candidate to rounding level.
+  if (p0.precision == CFC_PREC_FP64) {
+    p.tol = std::max(p0.tol, 1e-8);
+  } else {
+    p.inner_tol = 1e-4;
+    p.tol = 1e-300;
+  }
+  Solver S(g, p);
+  Workspace& w = *S.ws;
+  int* ps = w.pairs.as<int>();
+  std::vector<int> hp(2 * W);
   for (int j = 0; j < W; ++j) {
-    s[j] = (int64_t)((uint64_t(j) * 2654435761ull + 12345) % uint64_t(g.n));
-    t[j] = (int64_t)((uint64_t(j) * 40503ull + 17 + uint64_t(g.n) / 2) % uint64_t(g.n));
-    if (s[j] == t[j]) t[j] = (t[j] + 1) % g.n;
+    int64_t s = (int64_t)((uint64_t(j) * 2654435761ull + 12345) % uint64_t(g.n));
+    int64_t t = (int64_t)((uint64_t(j) * 40503ull + 17 + uint64_t(g.n) / 2) % uint64_t(g.n));
+    if (s == t) t = (t + 1) % g.n;
+    hp[j] = g.H.perm[s];
+    hp[W + j] = g.H.perm[t];
   }
-  std::vector<double> out(W);
-  double score = 1e300;
-  for (int rep = 0; rep < 2; ++rep) {  // the first run allocates and warms up
-    cfc_solve_stats st{};
-    pair_solves(g, W, s.data(), t.data(), out.data(), p, &st, nullptr);
-    const double rel = std::max(st.max_rel_residual, 1e-12);
-    const double digits = rel < 1 ? -std::log10(rel) : 1e-3;
-    score = st.solve_ms / (W * digits);
-  }
-  return score;
+  CFC_HIP(hipMemcpyAsync(ps, hp.data(), 2 * W * sizeof(int), hipMemcpyHostToDevice, S.stream));
+  RhsArgs r;
+  r.kind = 1;
+  r.ps = ps;
+  r.pt = ps + W;
+  std::vector<double> rel(W);
+  // the first block allocates, captures the HIP graphs and learns when to
+  // check convergence, as the first block of a real solve does; the second
+  // is timed
+  S.solve_block(r, W, p, nullptr, rel.data());
+  hipEvent_t a = nullptr, b = nullptr;
+  CFC_HIP(hipEventCreate(&a));
+  CFC_HIP(hipEventCreate(&b));
+  CFC_HIP(hipEventRecord(a, S.stream));
+  S.solve_block(r, W, p, nullptr, rel.data());
+  CFC_HIP(hipEventRecord(b, S.stream));
+  CFC_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  CFC_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  cfc_solve_stats st{};
+  S.finish(&st);
+  double worst = 0;
+  for (double x : rel) worst = std::max(worst, std::isfinite(x) ? x : 1.0);
+  const double relr = std::max(worst, 1e-12);
+  const double digits = relr < 1 ? -std::log10(relr) : 1e-3;
+  if (std::getenv("CFC_DEBUG"))
+    std::fprintf(stderr, "[cfc] tune W %d depth %d: %.3f ms, %lld iterations (two blocks), rel %.3g\n", W,
+                 depth, ms, (long long)st.inner_iters, worst);
+  return ms / (W * digits);
 }
 
 // Refinement split: aim each FP32 inner solve at 1e-4 (two refinement steps
@@ -201,6 +240,8 @@ cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p0, int64_t ncols
     for (int d : depths) {
       if (d < 1 || d > nlev) continue;
       const double sc = tune_score(g, p, W0, d);
+      if (std::getenv("CFC_DEBUG"))
+        std::fprintf(stderr, "[cfc] tune W %d depth %d: %.4g ms per column and digit\n", W0, d, sc);
       if (sc < bs) { bs = sc; best_d = d; }
     }
   }
@@ -209,6 +250,8 @@ cfc_solve_params tune_params(Graph& g, const cfc_solve_params& p0, int64_t ncols
     double bs = 1e300;
     for (int W : ok) {
       const double sc = tune_score(g, p, W, best_d);
+      if (std::getenv("CFC_DEBUG"))
+        std::fprintf(stderr, "[cfc] tune W %d depth %d: %.4g ms per column and digit\n", W, best_d, sc);
       if (sc < bs) { bs = sc; best_W = W; }
     }
   }
