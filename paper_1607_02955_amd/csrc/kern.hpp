@@ -65,8 +65,10 @@ struct LevelArgs {
 
 // Right-hand side of the FP64 residual kernel.
 struct RhsArgs {
-  int kind = 0;                  // 0 = dense FP64 n x W, 1 = pairs e_s - e_t
+  int kind = 0;                  // 0 = dense FP64 n x W, 1 = pairs e_s - e_t, 2 = dense FP32
   const double* dense = nullptr;
+  const float* dense32 = nullptr;  // kind 2 (may be residual64's own r_out: each row is read
+                                   // before it is overwritten)
   const int* ps = nullptr;       // [W] row of +1 (or -1 = none)
   const int* pt = nullptr;       // [W] row of -1 (or -1 = none)
   double* r64_out = nullptr;     // residual64: also store r in FP64 here (may be dense itself)

@@ -948,7 +948,7 @@ __device__ __forceinline__ Vec<double, V> ld_f64(const TX* p) {
 
 template <typename TO, int W, typename TX, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const TX* __restrict__ x,
-                                                       RhsArgs rhs, TO* __restrict__ r_out,
+                                                       RhsArgs rhs, TO* r_out,
                                                        double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
   using D = Deco<W, SPLIT>;
@@ -996,6 +996,10 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelArgs L, const TX* __
         const Vec<double, V> bb = ld_nt<double, V>(rhs.dense + o);
 #pragma unroll
         for (int i = 0; i < V; ++i) bv[i] = bb.v[i];
+      } else if (rhs.kind == 2) {
+        const Vec<float, V> bb = ld_nt<float, V>(rhs.dense32 + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) bv[i] = double(bb.v[i]);
       } else {
 #pragma unroll
         for (int i = 0; i < V; ++i) bv[i] = (u == ps[i] ? 1.0 : 0.0) - (u == pt[i] ? 1.0 : 0.0);

@@ -587,9 +587,9 @@ void Solver::capture_iterations() {
   for (int k = 0; k < 2; ++k) {
     CFC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     if (k == 0)
-      iteration(false, w.rb.p, w.ra.p);
+      iteration(false, w.rb.p, r_alt());
     else
-      iteration(false, w.ra.p, w.rb.p);
+      iteration(false, r_alt(), w.rb.p);
     CFC_HIP(hipStreamEndCapture(stream, &graph[k]));
     CFC_HIP(hipGraphInstantiate(&gexec[k], graph[k], nullptr, nullptr, 0));
   }
@@ -687,7 +687,7 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
   iteration(true, r0, w.rb.p);
   if (max_inner == 1 || (first_check <= 1 && 1 % check_every == 0 && converged())) return record(it);
   if (params.use_graph) {
-    // the residual is in r_b after odd iterations, in r_a after even ones
+    // the residual is in r_b after odd iterations, in r_alt() after even ones
     if (!gexec[0]) capture_iterations();
     while (it < max_inner) {
       CFC_HIP(hipGraphLaunch(gexec[it % 2 == 1 ? 0 : 1], stream));
@@ -699,7 +699,7 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
     return record(it);
   }
   void* ra = w.rb.p;  // current residual
-  void* rb = w.ra.p;
+  void* rb = r_alt();
   while (it < max_inner) {
     ++it;
     iteration(false, ra, rb);
@@ -729,6 +729,13 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   // needed more; otherwise the FP64 residual is kept for the next step
   const bool direct = p.precision == CFC_PREC_FP64 || p.inner_tol < 1e-6;
   bool r64_valid = false;  // ws.r64 = b - L x64 in FP64
+  // In Schur mode the inner solve leaves ws.ra (the FP32 residual it was
+  // given) untouched, so the next step reads r_prev from there in FP32.
+  // Rounding r_prev to FP32 moves the computed residual by at most
+  // 2^-24 |r_prev| per entry; those bounds are added up per column (ebound)
+  // and counted against the tolerance, so the FP64 test still certifies it.
+  const bool r32 = schur && !w.fp64;
+  std::vector<double> ebound(W, 0.0);
   for (;; ++step) {
     // x64 = x64_prev + d - mean(d) with d the FP32 inner solution still in
     // ws.x, and L 1 = 0, so b - L x64 = r_prev - L d up to FP64 rounding,
@@ -736,13 +743,18 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     // after later ones.  That residual gathers the FP32 d (half the bytes of
     // x64) and computes in FP64; without a kept residual (a step that was
     // expected to be the last) it gathers x64.
-    const bool x32 = have_x && !w.fp64 && (step == 1 || r64_valid);
+    const bool x32 = have_x && !w.fp64 && (step == 1 || r64_valid || r32);
     RhsArgs rr = rhs;
     if (x32 && step >= 2) {
-      rr.kind = 0;
-      rr.dense = w.r64.as<double>();
+      if (r32) {
+        rr.kind = 2;
+        rr.dense32 = static_cast<const float*>(w.ra.p);
+      } else {
+        rr.kind = 0;
+        rr.dense = w.r64.as<double>();
+      }
     }
-    const bool keep = !w.fp64 && have_x && (!direct || multi_step) && step < p.max_refine;
+    const bool keep = !r32 && !w.fp64 && have_x && (!direct || multi_step) && step < p.max_refine;
     if (keep) {
       if (!w.r64.p) w.r64.alloc(g->ctx, (size_t)d0.n * W * sizeof(double));
       rr.r64_out = w.r64.as<double>();
@@ -752,8 +764,9 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     if (!pre) {
       k.residual64(w.la64, have_x ? (x32 ? w.x.p : w.x64.p) : nullptr, x32 ? 1 : 0, rr, w.ra.p,
                    w.part_ptr(P_PQ), s);
-      bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) + (rr.kind == 0 ? 8.0 : 0.0) +
-                                   es + (keep ? 8.0 : 0.0)) +
+      bytes += d0.n * (double)W * ((have_x ? (x32 ? 4.0 : 8.0) : 0.0) +
+                                   (rr.kind == 0 ? 8.0 : (rr.kind == 2 ? 4.0 : 0.0)) + es +
+                                   (keep ? 8.0 : 0.0)) +
                (have_x ? mat_bytes(d0, !d0.unit, 8) : 0.0);
     }
     r64_valid = keep;
@@ -765,7 +778,7 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     cur_max = 0;
     for (int j = 0; j < W; ++j) {
       if (j >= ncols || !(b2[j] > 0)) { rel[j] = 0; continue; }
-      rel[j] = std::sqrt(r64[j] / b2[j]);
+      rel[j] = (std::sqrt(r64[j]) + ebound[j]) / std::sqrt(b2[j]);
       if (!std::isfinite(rel[j])) continue;
       cur_max = std::max(cur_max, rel[j]);
       if (rel[j] > p.tol) all = false;
@@ -775,6 +788,10 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
                    cur_max, rel[0]);
     }
     if (all || step >= p.max_refine) break;
+    // the next step reads this residual rounded to FP32 (ws.ra); from the
+    // second step on that is the previous residual, not b
+    if (r32 && step >= 1)
+      for (int j = 0; j < W; ++j) ebound[j] += 0x1p-24 * std::sqrt(std::max(r64[j], 0.0));
     // Inner target as a fraction of what is left to reach tol: 0.9 when the
     // inner solve can be trusted to land near it (FP64 inner solves, or FP32
     // ones aimed straight at the target, inner_tol < 1e-6); 0.5 when FP32

@@ -68,6 +68,9 @@ struct Solver {
   int base = 0;  // level the inner CG runs on (1 in Schur mode)
   bool jac_top = false;  // the preconditioner is one Jacobi step on level `base`
   void* r0 = nullptr;  // the inner CG's initial residual (ws.ra, or ws.rt in Schur mode)
+  // the residual buffer the iterations alternate with ws.rb: ws.ra, or in
+  // Schur mode ws.rt, so that ws.ra keeps the level-0 residual
+  void* r_alt() const { return schur ? ws->rt.p : ws->ra.p; }
   bool xfu = false;  // x updates applied by the product kernel
   bool multi_step = false;  // a block of this solve took more than one refinement step
   // FP32/FP64 blocks streamed by the level-0 CG update (r_in, q, x, p read;
