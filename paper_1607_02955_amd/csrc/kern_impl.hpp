@@ -233,11 +233,18 @@ __device__ __forceinline__ T wt(const T* w, int e) {
 #define CFC_GATHER_DEPTH 4
 #endif
 constexpr int kGatherDepth = CFC_GATHER_DEPTH;
+// rows in flight in the FP32 heavy-row pre-pass, whose segments are long
+// (R-MAT-20's operator product 3.89 against 3.97 ms at 4; the FP64
+// residual's pre-pass was slower at 8)
+#ifndef CFC_HEAVY_GATHER_DEPTH
+#define CFC_HEAVY_GATHER_DEPTH 8
+#endif
+constexpr int kHeavyGatherDepth = CFC_HEAVY_GATHER_DEPTH;
 
-template <typename T, int W, int NSX = slices_of(W), class F>
+template <typename T, int W, int NSX = slices_of(W), int D = kGatherDepth, class F>
 __device__ __forceinline__ void gather_acc(T* nb, const int* __restrict__ col, const T* __restrict__ w,
                                            int e0, int e1, int s, int S, F&& f) {
-  constexpr int V = Shape<W, NSX>::V, D = kGatherDepth;
+  constexpr int V = Shape<W, NSX>::V;
   int e = e0 + s;
   for (; e + (D - 1) * S < e1; e += D * S) {
     int v[D];
@@ -330,6 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
                                                   const T* __restrict__ q, const T* __restrict__ xc,
                                                   const double* __restrict__ scal) {
   constexpr int LPR = Shape<W, NSX>::LPR, V = Shape<W, NSX>::V, RG = Shape<W, NSX>::RG, WS = Shape<W, NSX>::WS;
+  constexpr int HD = sizeof(T) == 4 ? kHeavyGatherDepth : kGatherDepth;
   __shared__ T ldc[RG * WS];
   int slice, sgi, nsg;
   slice_of_block<W, NSX>(slice, sgi, nsg);
@@ -347,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(LevelArgs L, const T* __restri
     T nb[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) nb[i] = 0;
-    gather_acc<T, W, NSX>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
+    gather_acc<T, W, NSX, HD>(nb, L.hcol, w, L.seg_e[sgi], L.seg_e[sgi + 1], rg, RG, [&](int v) {
       if constexpr (KIND == HK_F8)
         return ld_f8<T, V>(reinterpret_cast<const f8_t*>(a) + (size_t)v * W + c0,
                            zsc[(size_t)v * Shape<W, NSX>::NS + slice]);
