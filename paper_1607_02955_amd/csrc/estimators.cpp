@@ -56,13 +56,14 @@ void check_params(const cfc_solve_params& p) {
 // ---------------------------------------------------------------------------
 // Autotuner: the block width W and the V-cycle depth that minimise device
 // time per solved column.  Each candidate solves W sample pair right-hand
-// sides for one refinement step (inner tolerance 1e-3, at most 100 PCG
-// iterations) and is scored by solve time / (W * decades of residual
-// reduction), after a warm-up run.  Depth is chosen first at W = 256 (or
-// the fixed W), then W at that depth, then (inner_tol = 0) the refinement
-// split (tune_split below).  Results are cached in the graph and, when
-// CFC_TUNE_CACHE names a file, on disk as "n nnz levels precision
-// requested-W W depth one-step" lines.
+// sides for one refinement step (to the reduction a real inner solve is
+// asked for, at most 200 PCG iterations) twice with one solver, and is
+// scored by the second block's time / (W * decades of residual
+// reduction).  Depth is chosen first at W = 256 (or the fixed W), then W
+// at that depth, then (inner_tol = 0) the refinement split (tune_split
+// below).  Results are cached in the graph and, when CFC_TUNE_CACHE names
+// a file, on disk as "n nnz levels precision requested-W W depth one-step"
+// lines.
 
 static std::string tune_key(const Graph& g, int prec) {
   std::ostringstream o;
@@ -365,8 +366,9 @@ void pair_solves(Graph& g, int64_t npairs, const int64_t* s, const int64_t* t, d
     r.kind = 1;
     r.ps = ps;
     r.pt = pt;
+    S.pair_out = dd;
     S.solve_block(r, nc, p, stat.data(), nullptr);
-    pair_diff(W, nc, w.x64.as<double>(), ps, pt, dd, S.stream);
+    if (!S.pair_used) pair_diff(W, nc, w.x64.as<double>(), ps, pt, dd, S.stream);
     CFC_HIP(hipMemcpyAsync(res.data(), dd, nc * sizeof(double), hipMemcpyDeviceToHost, S.stream));
     CFC_HIP(hipStreamSynchronize(S.stream));
     for (int j = 0; j < nc; ++j) {

@@ -181,6 +181,10 @@ enum FinOp { F_ALPHA = 0, F_RZINIT = 1, F_BETA = 2, F_R64 = 3, F_CS = 4 };
 // receives the S_RR and S_R64 rows, so the host reads them without a copy.
 void finalize(int W, int op, int g0, const double* p0, int g1, const double* p1, int g2,
               const double* p2, double* scal, hipStream_t s, double* host = nullptr);
+// out[j] = (first ? 0 : out[j]) + d[s_j, j] - d[t_j, j] for j < ncols (FP32
+// d, FP64 sum; 0 where s_j or t_j is -1)
+void pair_acc(int W, int ncols, const float* d, const int* ps, const int* pt, double* out, int first,
+              hipStream_t s);
 // out[j] = x64[s_j, j] - x64[t_j, j] for j < ncols
 void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt, double* out,
                hipStream_t s);

@@ -143,6 +143,15 @@ __global__ void k_pair_diff(int W, int ncols, const double* __restrict__ x,
   out[j] = (s >= 0 && t >= 0) ? x[(size_t)s * W + j] - x[(size_t)t * W + j] : 0.0;
 }
 
+__global__ void k_pair_acc(int W, int ncols, const float* __restrict__ d, const int* __restrict__ ps,
+                           const int* __restrict__ pt, double* __restrict__ out, int first) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  const int s = ps[j], t = pt[j];
+  const double v = (s >= 0 && t >= 0) ? double(d[(size_t)s * W + j]) - double(d[(size_t)t * W + j]) : 0.0;
+  out[j] = first ? v : out[j] + v;
+}
+
 __global__ void k_gather(int q, const double* __restrict__ src, const int* __restrict__ idx,
                          double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,6 +331,13 @@ void pair_diff(int W, int ncols, const double* x64, const int* ps, const int* pt
   if (ncols <= 0) return;
   hipLaunchKernelGGL(k_pair_diff, dim3((ncols + 255) / 256), dim3(256), 0, s, W, ncols, x64, ps, pt,
                      out);
+}
+
+void pair_acc(int W, int ncols, const float* d, const int* ps, const int* pt, double* out, int first,
+              hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_pair_acc, dim3((ncols + 255) / 256), dim3(256), 0, s, W, ncols, d, ps, pt, out,
+                     first);
 }
 
 void gather(int q, const double* src, const int* idx, double* out, hipStream_t s) {

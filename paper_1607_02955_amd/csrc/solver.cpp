@@ -648,10 +648,13 @@ int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner,
   // the level-1 iterations never touch), then the column sums of d over all
   // rows for the mean projection
   k.elim_back(w.la[0], w.ra.p, w.x.p, w.part_ptr(P_RZ), 0, 0, stream);
-  k.dot(n, w.x.p, nullptr, w.part_ptr(P_CS), stream);
-  finalize(w.W, F_CS, grid_for(n, k.rg), w.part_ptr(P_CS), 0, nullptr, 0, nullptr, w.scal.as<double>(),
-           stream);
-  bytes += (n - nc) * (double)w.W * es * 2 + 2.0 * (n - nc) * w.W * es + 16.0 * (n - nc) + n * (double)w.W * es;
+  bytes += (n - nc) * (double)w.W * es * 2 + 2.0 * (n - nc) * w.W * es + 16.0 * (n - nc);
+  if (!pairs_now) {  // pair differences need no mean
+    k.dot(n, w.x.p, nullptr, w.part_ptr(P_CS), stream);
+    finalize(w.W, F_CS, grid_for(n, k.rg), w.part_ptr(P_CS), 0, nullptr, 0, nullptr,
+             w.scal.as<double>(), stream);
+    bytes += n * (double)w.W * es;
+  }
   return it;
 }
 
@@ -736,6 +739,12 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   // and counted against the tolerance, so the FP64 test still certifies it.
   const bool r32 = schur && !w.fp64;
   std::vector<double> ebound(W, 0.0);
+  // Pair right-hand sides whose caller only wants x[s_j] - x[t_j]: in FP32
+  // Schur mode no residual reads x64 (they gather the FP32 corrections), so
+  // each step's correction d adds d[s_j] - d[t_j] to pair_out[j] (the mean
+  // projection cancels in the difference) and x64 is not formed.
+  pairs_now = pair_out && r32 && rhs.kind == 1;
+  pair_used = pairs_now;
   for (;; ++step) {
     // x64 = x64_prev + d - mean(d) with d the FP32 inner solution still in
     // ws.x, and L 1 = 0, so b - L x64 = r_prev - L d up to FP64 rounding,
@@ -805,13 +814,23 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     cur_step = -1;
     if (debug) std::fprintf(stderr, "[cfc]   pcg its %d (inner tol %.2e)\n", its, itol);
     inner_iters += its;
-    k.xupdate64(d0.n, w.x64.as<double>(), w.x.p, w.scal.as<double>(), have_x ? 0 : 1, s);
-    bytes += d0.n * (double)W * ((have_x ? 16.0 : 8.0) + es);
+    if (pairs_now) {
+      pair_acc(W, ncols, static_cast<const float*>(w.x.p), rhs.ps, rhs.pt, pair_out, have_x ? 0 : 1, s);
+    } else {
+      k.xupdate64(d0.n, w.x64.as<double>(), w.x.p, w.scal.as<double>(), have_x ? 0 : 1, s);
+      bytes += d0.n * (double)W * ((have_x ? 16.0 : 8.0) + es);
+    }
     have_x = true;
     refine_steps++;
     if (step >= 1) multi_step = true;
   }
-  if (!have_x) k.zero(w.x64.p, (size_t)d0.n * W * 8, s);
+  if (!have_x) {
+    if (pairs_now)
+      zero_fill(pair_out, (size_t)W * sizeof(double), s);
+    else
+      k.zero(w.x64.p, (size_t)d0.n * W * 8, s);
+  }
+  pairs_now = false;
   for (int j = 0; j < ncols; ++j) {
     int32_t st = CFC_COL_OK;
     if (!(b2[j] > 0)) st = (b2[j] == 0) ? CFC_COL_SKIPPED : CFC_COL_DIVERGED;

@@ -68,6 +68,12 @@ struct Solver {
   int base = 0;  // level the inner CG runs on (1 in Schur mode)
   bool jac_top = false;  // the preconditioner is one Jacobi step on level `base`
   void* r0 = nullptr;  // the inner CG's initial residual (ws.ra, or ws.rt in Schur mode)
+  // Set by the caller of solve_block for pair right-hand sides: device
+  // double[W] that receives x[s_j] - x[t_j] directly (FP32 Schur mode only;
+  // pair_used tells whether the last block did so, else x64 holds x).
+  double* pair_out = nullptr;
+  bool pair_used = false;
+  bool pairs_now = false;  // inside solve_block: the current block does
   // the residual buffer the iterations alternate with ws.rb: ws.ra, or in
   // Schur mode ws.rt, so that ws.ra keeps the level-0 residual
   void* r_alt() const { return schur ? ws->rt.p : ws->ra.p; }
