@@ -482,6 +482,33 @@ def test_bf16_z_matches_fp32_z(ctx, case, monkeypatch):
     np.testing.assert_allclose(res["111"], res["110"], rtol=1e-12, atol=1e-15)
 
 
+def test_pair_differences_without_x64(ctx):
+    """Pair solves in FP32 Schur mode add x[s] - x[t] per refinement step
+    instead of forming the mean-zero x64: the result equals the difference
+    taken from full solves of the same right-hand sides (dense path), and
+    the oracle's resistances, over several refinement steps and with a pair
+    whose ends coincide (resistance 0)."""
+    eg = leafy_graph(seed=77)
+    g = load(ctx, eg, coarsest_max=64, eliminate=2, max_complexity=-1)
+    assert g.info()["eliminated"] > 0
+    _, Rm = dense_R(eg)
+    rng = np.random.default_rng(77)
+    s = rng.integers(0, eg.n, 70)
+    t = rng.integers(0, eg.n, 70)
+    t[5] = s[5]
+    for depth in (2, 0):
+        r, st = g.resistance(s, t, block=64, tol=1e-9, levels=depth, stats=True)
+        say("pair acc", depth, st["refine_steps"], st["inner_iters"], st["max_rel_residual"])
+        assert st["refine_steps"] >= 2 * st["blocks"]  # more than one refinement step per block
+        np.testing.assert_allclose(r, Rm[s, t], rtol=1e-8, atol=1e-12)
+        assert r[5] == 0.0
+        B = np.zeros((len(s), eg.n))
+        B[np.arange(len(s)), s] += 1.0
+        B[np.arange(len(s)), t] -= 1.0
+        X = g.solve(B, block=64, tol=1e-9, levels=depth)
+        np.testing.assert_allclose(r, X[np.arange(len(s)), s] - X[np.arange(len(s)), t], rtol=1e-7, atol=1e-12)
+
+
 def test_elimination_to_two_nodes_is_exact(ctx):
     """A star loses every leaf but one: the elimination level over a two-node
     coarsest level is an exact solver."""
