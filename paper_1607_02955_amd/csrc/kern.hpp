@@ -88,8 +88,9 @@ struct KernTable {
   int (*rows_grid)(const LevelArgs&, int units);
   // The FP8 paths (spmm_pq jac = 3, jacobi / update_jacobi zf = 2) slice
   // the columns ns8 ways (half the regular count) with rg8 row groups per
-  // workgroup: their partial sums have rows_grid8 / grid_for(units, rg8)
-  // rows, and the scales of an FP8 z are float[n][ns8].
+  // workgroup and up to twice the workgroups per slice: their partial sums have
+  // rows_grid8 / grid_for(units, rg8, slices_of(W) / ns8) rows, and the
+  // scales of an FP8 z are float[n][ns8].
   int rg8 = 0;
   int ns8 = 0;
   int (*rows_grid8)(const LevelArgs&, int units);
@@ -172,7 +173,7 @@ struct KernTable {
 
 // Tables for element type float (FP32 inner solver) and double.
 const KernTable* kern_table(int W, bool fp64);
-int grid_for(int units, int rows_per_block);
+int grid_for(int units, int rows_per_block, int cap_scale = 1);
 
 // Sum partials[g][W] over g (fixed order) into scal rows; op selects the
 // scalar update (see Finalize in kern_impl.hpp).

@@ -31,7 +31,7 @@ const KernTable* kern_table(int W, bool fp64) {
   }
 }
 
-int grid_for(int units, int rg) {
+int grid_for(int units, int rg, int cap_scale) {
   // Workgroups per column slice.  Large levels take 1024 (8192 in all at
   // eight slices, four rounds of the 2048 that are resident at once); levels
   // of at most 8192 row tiles take 512, so that each workgroup walks at
@@ -39,13 +39,19 @@ int grid_for(int units, int rg) {
   // level-0 kernels: BA-100k projection +2.4% at 512, R-MAT-20 and
   // road-2048 levels 5-6% slower there).  CFC_GRID_CAP fixes one cap for
   // every level, at most kMaxGrid (the partial-sum buffers' row count).
+  // cap_scale > 1 (kernels that slice the columns fewer ways) raises the
+  // cap up to that factor, as far as each workgroup still walks 16 tiles
+  // (R-MAT-20's FP8 product, 43k tiles: 3.73 against 3.91 ms at twice the
+  // cap; BA-100k's, 8k tiles, was slower at twice the cap).
   static const int fixed = [] {
     const char* e = std::getenv("CFC_GRID_CAP");
     return e ? std::max(8, std::min(kMaxGrid, std::atoi(e))) : 0;
   }();
   if (units <= 0) return 0;
   int tiles = (units + rg - 1) / rg;
-  const int cap = fixed ? fixed : (tiles <= 8192 ? kMaxGrid / 4 : kMaxGrid / 2);
+  int cap = fixed ? fixed : (tiles <= 8192 ? kMaxGrid / 4 : kMaxGrid / 2);
+  if (cap_scale > 1) cap = std::min(cap * cap_scale, std::max(cap, tiles / 16));
+  cap = std::min(cap, kMaxGrid);
   int g = std::min(tiles, cap);
   if (g >= 64) g &= ~7;
   return g;

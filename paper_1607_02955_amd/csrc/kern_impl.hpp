@@ -1475,7 +1475,7 @@ struct Launch {
   }
   // the same for the FP8 product (row splits of at most 4)
   static int rows_grid8(const LevelArgs& L, int units) {
-    return grid_for(units, RG8 / (L.split >= 4 ? 4 : 1));
+    return grid_for(units, RG8 / (L.split >= 4 ? 4 : 1), NS / NS8);
   }
 
 #define CFC_LAUNCH(K, units, ...)                                                              \
@@ -1572,7 +1572,7 @@ struct Launch {
     const int g = grid_units(L.n, RG);
     if (!g) return;
     if (zf == 2 && part)
-      hipLaunchKernelGGL((k_jacobi<T, W, true, 2, NS8>), dim3(grid_units(L.n, RG8) * NS8), dim3(kBlock),
+      hipLaunchKernelGGL((k_jacobi<T, W, true, 2, NS8>), dim3(grid_for(L.n, RG8, NS / NS8) * NS8), dim3(kBlock),
                          0, s, L, (const T*)b, x, part);
     else if (zf && part)
       hipLaunchKernelGGL((k_jacobi<T, W, true, 1>), dim3(g * NS), dim3(kBlock), 0, s, L,
@@ -1593,7 +1593,7 @@ struct Launch {
   hipLaunchKernelGGL((k_update_jacobi<T, W, ZF>), dim3(g * NS), dim3(kBlock), 0, s, L, (const T*)r_in, \
                      (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal, first, prr, pcs, prz, xf)
     if (zf == 2)
-      hipLaunchKernelGGL((k_update_jacobi<T, W, 2, NS8>), dim3(grid_units(L.n, RG8) * NS8), dim3(kBlock),
+      hipLaunchKernelGGL((k_update_jacobi<T, W, 2, NS8>), dim3(grid_for(L.n, RG8, NS / NS8) * NS8), dim3(kBlock),
                          0, s, L, (const T*)r_in, (const T*)q, (const T*)p, (T*)x, (T*)r_out, z, scal,
                          first, prr, pcs, prz, xf);
     else if (zf)

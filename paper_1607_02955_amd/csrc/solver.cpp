@@ -369,14 +369,14 @@ void Solver::vcycle(bool update, bool first_x, const void* r_in, void* r_out) {
       const double ub = db.n * nw * upd_blocks(first_x) + 2.0 * es * db.n + (bfz ? zbytes() * db.n * w.W : 0.0);
       prof_end(K_RESTRICT0, ub);
       bytes += ub;
-      g_rr = grid_for(db.n, zf8 ? k.rg8 : k.rg);
+      g_rr = zf8 ? grid_for(db.n, k.rg8, slices_of(w.W) / k.ns8) : grid_for(db.n, k.rg);
       g_cs = xfu ? 0 : g_rr;  // with xfu the sums of x come with the last update
     } else {
       // r . S r (and the bfloat16 copy of z = S r when the product gathers it)
       k.jacobi(lb, r_in, bfz ? w.z.p : nullptr, w.part_ptr(P_RZ), zfmt(), s);
       bytes += db.n * nw + es * db.n + (bfz ? zbytes() * db.n * w.W : 0.0);
     }
-    g_rz = grid_for(db.n, zf8 ? k.rg8 : k.rg);
+    g_rz = zf8 ? grid_for(db.n, k.rg8, slices_of(w.W) / k.ns8) : grid_for(db.n, k.rg);
     return;
   }
   if (!schur && d0.nC > 0 && L >= 2) {
