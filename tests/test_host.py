@@ -299,10 +299,32 @@ def test_locality_orders_give_valid_nested_hierarchies(hctx, order):
         assert deg[np.argsort(p)[0]] == deg.max()
 
 
+@pytest.mark.parametrize("nest", [1, 2])
+def test_nesting_depth_only_renumbers(hctx, nest):
+    """Nesting the numbering through every aggregation level or through the
+    kept levels only gives the same levels (sizes and entries), a valid
+    permutation and contiguous aggregates; only the order differs."""
+    eg = synth.barabasi_albert(1500, 4, seed=8)
+    ref = cfc.Graph.from_edgelist(hctx, eg).build_hierarchy(coarsest_max=64, nest=0)
+    g = cfc.Graph.from_edgelist(hctx, eg).build_hierarchy(coarsest_max=64, nest=nest)
+    assert g.info()["level_n"] == ref.info()["level_n"]
+    assert g.info()["level_nnz"] == ref.info()["level_nnz"]
+    lv0 = g.level(0)
+    p = lv0["perm"]
+    assert sorted(p.tolist()) == list(range(eg.n))
+    np.testing.assert_allclose(_level_laplacian(lv0)[np.ix_(p, p)], LAP.of(eg).toarray(), atol=1e-12)
+    for l in range(g.info()["levels"] - 1):
+        lv = g.level(l)
+        if lv["elimination"]:
+            _check_elimination_level(lv, g.level(l + 1))
+        else:
+            assert np.all(np.diff(lv["agg"]) >= 0)
+
+
 def test_setup_param_errors_enums(hctx):
     eg = synth.path_graph(10)
     g = cfc.Graph.from_edgelist(hctx, eg)
     for kw in ({"order": 4}, {"eliminate": 3}, {"device": 3}, {"elim_degree": 5},
-               {"elim_degree": -1}):
+               {"elim_degree": -1}, {"nest": 3}, {"nest": -1}):
         with pytest.raises(cfc.CfcError):
             g.build_hierarchy(**kw)
