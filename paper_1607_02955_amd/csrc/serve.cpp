@@ -261,8 +261,14 @@ void GraphWorker::run() {
         continue;
       }
       // one refinement step for every live slot
+      // each slot aims at its own remaining reduction to tol
       const double aim = (p.precision == CFC_PREC_FP64 || p.inner_tol < 1e-6) ? 0.9 : 0.5;
-      const double itol = std::min(0.5, std::max(p.inner_tol, aim * p.tol / std::max(cur_max, 1e-300)));
+      std::vector<double> itol(W, 0.5);
+      for (int j = 0; j < W; ++j) {
+        const double rel = std::sqrt(r64[j] / 2.0);
+        const double relj = (busy[j] && rel > 0 && std::isfinite(rel)) ? rel : std::max(cur_max, 1e-300);
+        itol[j] = std::min(0.5, std::max(p.inner_tol, aim * p.tol / relj));
+      }
       sol->pcg(r64, itol, p.max_inner, 1);
       w.kt->xupdate64(w.la64.n, w.x64.as<double>(), w.x.p, w.scal.as<double>(), 0, stream);
       for (int j = 0; j < W; ++j)

@@ -604,13 +604,14 @@ void Solver::capture_iterations() {
 // the iteration count.  After the first iteration the residual alternates
 // between ws.rb and ws.ra; with use_graph the later iterations replay a
 // captured pair of iterations.
-int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every) {
+int Solver::pcg(const std::vector<double>& rr0, const std::vector<double>& itol, int max_inner,
+                int check_every) {
   Workspace& w = *ws;
   const KernTable& k = *w.kt;
   const double es = w.fp64 ? 8 : 4;
   if (!schur) {
     r0 = w.ra.p;
-    const int it = pcg_iterations(rr0, inner_tol, max_inner, check_every);
+    const int it = pcg_iterations(rr0, itol, max_inner, check_every);
     if (xfu) {
       // the product kernels applied every x update but the last one
       const DevLevel& d0 = g->D->lv[0];
@@ -641,7 +642,7 @@ int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner,
     if (!(rr0[j] > 0)) rrt[j] = 0;  // columns the caller left out stay out
   bytes += nc * w.W * es;
   r0 = w.rt.p;
-  const int it = pcg_iterations(rrt, inner_tol, max_inner, check_every);
+  const int it = pcg_iterations(rrt, itol, max_inner, check_every);
   if (xfu) {
     k.xfinal(nc, w.x.p, w.p.p, w.scal.as<double>(), w.part_ptr(P_CS), stream);
     bytes += 3.0 * nc * w.W * es;
@@ -660,17 +661,21 @@ int Solver::pcg(const std::vector<double>& rr0, double inner_tol, int max_inner,
   return it;
 }
 
-int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int max_inner,
+int Solver::pcg_iterations(const std::vector<double>& rr0, const std::vector<double>& itol, int max_inner,
                            int check_every) {
   Workspace& w = *ws;
   const int W = w.W;
   vcycle(false, false, r0, nullptr);
   finalize(W, F_RZINIT, g_rz, w.part_ptr(P_RZ), 0, nullptr, 0, nullptr, w.scal.as<double>(), stream);
-  std::vector<double> rr(W);
-  const double tol2 = inner_tol * inner_tol;
+  std::vector<double> rr(W), tol2(W);
+  double tight = 1;  // the strictest target of a tested column
+  for (int j = 0; j < W; ++j) {
+    tol2[j] = itol[j] * itol[j];
+    if (rr0[j] > 0) tight = std::min(tight, itol[j]);
+  }
   // no convergence test (and so no host synchronisation) before the fewest
   // iterations an earlier block needed at this refinement step, less one
-  const std::array<int, 3> key{nuse, cur_step, (int)std::lround(4.0 * std::log10(std::max(inner_tol, 1e-300)))};
+  const std::array<int, 3> key{nuse, cur_step, (int)std::lround(4.0 * std::log10(std::max(tight, 1e-300)))};
   const auto hit = cur_step >= 0 ? w.min_its.find(key) : w.min_its.end();
   const int first_check = hit != w.min_its.end() ? std::max(1, hit->second - 1) : 1;
   auto record = [&](int n_it) {
@@ -684,7 +689,7 @@ int Solver::pcg_iterations(const std::vector<double>& rr0, double inner_tol, int
     for (int j = 0; j < W; ++j) {
       if (!(rr0[j] > 0)) continue;
       if (!std::isfinite(rr[j])) continue;  // reported by the outer residual
-      if (rr[j] > tol2 * rr0[j]) return false;
+      if (rr[j] > tol2[j] * rr0[j]) return false;
     }
     return true;
   };
@@ -724,7 +729,7 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
   const int W = w.W;
   const DevLevel& d0 = g->D->lv[0];
   const size_t es = w.fp64 ? 8 : 4;
-  std::vector<double> r64(W), b2(W), rel(W, 0.0);
+  std::vector<double> r64(W), b2(W), rel(W, 0.0), itol(W);
   bool have_x = false;
   const int gres = k.rows_grid(w.la64, d0.n);
   double cur_max = 1.0;
@@ -806,15 +811,23 @@ void Solver::solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& 
     // Inner target as a fraction of what is left to reach tol: 0.9 when the
     // inner solve can be trusted to land near it (FP64 inner solves, or FP32
     // ones aimed straight at the target, inner_tol < 1e-6); 0.5 when FP32
-    // rounding may leave the true residual above the recursive one.
+    // rounding may leave the true residual above the recursive one.  Each
+    // column is held to its own remaining reduction, aim tol / rel_j: one
+    // block's columns can stand decades apart after a step, and those near
+    // tol need not follow the worst one down.
     const double aim = direct ? 0.9 : 0.5;
-    double itol = p.precision == CFC_PREC_FP64 ? std::max(aim * p.tol / cur_max, 1e-15)
-                                                : std::max(p.inner_tol, aim * p.tol / cur_max);
-    itol = std::min(itol, 0.5);
+    double tight = 0.5;
+    for (int j = 0; j < W; ++j) {
+      const double relj = (rel[j] > 0 && std::isfinite(rel[j])) ? rel[j] : std::max(cur_max, 1e-300);
+      const double t = p.precision == CFC_PREC_FP64 ? std::max(aim * p.tol / relj, 1e-15)
+                                                     : std::max(p.inner_tol, aim * p.tol / relj);
+      itol[j] = std::min(t, 0.5);
+      if (j < ncols && b2[j] > 0) tight = std::min(tight, itol[j]);
+    }
     cur_step = step;
     const int its = pcg(r64, itol, p.max_inner, std::max(1, p.check_every));
     cur_step = -1;
-    if (debug) std::fprintf(stderr, "[cfc]   pcg its %d (inner tol %.2e)\n", its, itol);
+    if (debug) std::fprintf(stderr, "[cfc]   pcg its %d (strictest inner tol %.2e)\n", its, tight);
     inner_iters += its;
     if (pairs_now) {
       pair_acc(W, ncols, static_cast<const float*>(w.x.p), rhs.ps, rhs.pt, pair_out, have_x ? 0 : 1, s);

@@ -117,8 +117,11 @@ struct Solver {
   void capture_iterations();
   void vcycle(bool update, bool first_x, const void* r_in, void* r_out);
   void vcycle_elim(bool update, bool first_x, const void* r_in, void* r_out);
-  int pcg(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
-  int pcg_iterations(const std::vector<double>& rr0, double inner_tol, int max_inner, int check_every);
+  // itol[j]: the reduction of column j's residual norm the inner solve
+  // stops at (columns with rr0[j] <= 0 are not tested)
+  int pcg(const std::vector<double>& rr0, const std::vector<double>& itol, int max_inner, int check_every);
+  int pcg_iterations(const std::vector<double>& rr0, const std::vector<double>& itol, int max_inner,
+                     int check_every);
   void solve_block(const RhsArgs& rhs, int ncols, const cfc_solve_params& p, int32_t* status,
                    double* final_rel);
   void read_scal(int which, double* out);
