@@ -117,12 +117,14 @@ void upload_hierarchy(Graph& g) {
   const int L = (int)H.lv.size();
   D->lv.resize(L);
   hipStream_t s = c->stream;
-  // rows longer than 256 entries are summed by 256-edge segments (measured:
-  // R-MAT-20's operator product 6.4 -> 5.0 ms at W = 256 against a 512
-  // threshold; BA-100k slightly faster; CFC_HEAVY_DEG overrides)
+  // rows longer than 64 entries are summed by segments in the pre-pass: in
+  // the row kernels a long row holds up its whole workgroup (W = 512, FP8
+  // z: R-MAT-20 Sampling 8,972 / 9,414 / 9,434 RHS/s at thresholds 256 / 64
+  // / 96, BA-100k projection 72,785 / 78,611 / 76,062, 48 and 32 no better;
+  // earlier, at W = 256, 256 had beaten 512; CFC_HEAVY_DEG overrides)
   static const int heavy_deg = [] {
     const char* e = std::getenv("CFC_HEAVY_DEG");
-    return e ? std::max(16, std::atoi(e)) : 256;
+    return e ? std::max(16, std::atoi(e)) : 64;
   }();
   // edges per heavy-row segment (one pre-pass workgroup per segment and
   // slice): 512 (R-MAT-20 Sampling at W = 512 with FP8 z: operator product
