@@ -173,7 +173,7 @@ static bool width_fits(const Graph& g, int W, int prec) {
   for (const auto& l : g.D->lv) n += (double)l.n;
   const double n0 = (double)g.D->lv[0].n;
   const double es = prec == CFC_PREC_FP64 ? 8 : 4;
-  const double need = (n0 * (6 * es + 16) + 2 * (n - n0) * es) * W * 1.1;
+  const double need = ((n0 * (6 * es + 16) + 2 * (n - n0) * es) * W + (double)heavy_partial_bytes(g, W)) * 1.1;
   const uint64_t budget = g.ctx->budget;
   if (budget && g.ctx->in_use + need > (double)budget) return false;
   size_t freeb = 0, totalb = 0;

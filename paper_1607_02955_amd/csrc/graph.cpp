@@ -120,4 +120,11 @@ Graph* load_graph(Ctx* ctx, int64_t n, int64_t m, const int64_t* u, const int64_
   return g.release();
 }
 
+uint64_t heavy_partial_bytes(const Graph& g, int W) {
+  uint64_t rows = 0;
+  for (const DevLevel& d : g.D->lv) rows += (uint64_t)d.nseg + d.nheavy;
+  if (g.D->lv[0].nC > 0) rows += (uint64_t)g.D->fwd.nseg + g.D->fwd.nheavy;
+  return rows * W * 8;
+}
+
 }  // namespace cfc

@@ -167,6 +167,10 @@ struct Graph {
 // graph.cpp
 Graph* load_graph(Ctx* ctx, int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                   const double* w, uint32_t flags);
+// Device bytes of a width-W workspace's heavy-row partial sums: the segment
+// partials and per-row sums of every level and of the forward operator,
+// FP64-sized, as the solver allocates them (for memory estimates).
+uint64_t heavy_partial_bytes(const Graph& g, int W);
 // hierarchy.cpp
 void build_hierarchy(Graph& g, const cfc_setup_params& p);
 void upload_hierarchy(Graph& g);

@@ -107,7 +107,8 @@ static uint64_t workspace_bytes(const Graph& g, int W) {
   uint64_t n = 0;
   for (const auto& l : g.D->lv) n += (uint64_t)l.n;
   const uint64_t n0 = (uint64_t)g.D->lv[0].n;
-  return n0 * W * (6 * 4 + 8) + 2 * (n - n0) * W * 4 + (uint64_t)P_COUNT * kMaxGrid * W * 8;
+  return n0 * W * (6 * 4 + 8) + 2 * (n - n0) * W * 4 + (uint64_t)P_COUNT * kMaxGrid * W * 8 +
+         heavy_partial_bytes(g, W);
 }
 
 void GraphWorker::run() {
