@@ -261,8 +261,8 @@ void GraphWorker::run() {
         for (int j : fin) hp[j] = hp[W + j] = -1;
         continue;
       }
-      // one refinement step for every live slot
-      // each slot aims at its own remaining reduction to tol
+      // one refinement step for every live slot, each aiming at its own
+      // remaining reduction to tol
       const double aim = (p.precision == CFC_PREC_FP64 || p.inner_tol < 1e-6) ? 0.9 : 0.5;
       std::vector<double> itol(W, 0.5);
       for (int j = 0; j < W; ++j) {
