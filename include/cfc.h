@@ -192,7 +192,10 @@ typedef struct {
                             least the one that reaches tol); 0 = autotuned
                             (default): 1e-4 (FP32 inner solves, two
                             refinement steps to 1e-6) or 1e-7 (straight to
-                            the target) by timing both on sample columns */
+                            the target) by timing both on sample columns.
+                            Each column stops at its own reduction: the
+                            larger of inner_tol and a fraction of what its
+                            FP64 residual still lacks to reach tol */
   int32_t use_graph;     /* 1 = replay a captured HIP graph per PCG iteration */
   int32_t check_every;   /* PCG iterations between host convergence checks (1) */
   int32_t levels;        /* V-cycle depth: hierarchy levels used by the
