@@ -149,9 +149,10 @@ struct KernTable {
   void (*jl_rownorm)(int n, const double* x64, int ncols, double* N, double* part_cs, hipStream_t);
   void (*zero)(void* p, size_t bytes, hipStream_t);
   // Elimination level, forward step over the kept rows (lf = the forward
-  // operator, lf.n = kept rows): t = r + F r.  jac = 0 writes t to out;
-  // jac = 1 writes z = sd1 * t and partial sums of r . z (grid rows_grid);
-  // jac = 2 does the same with z stored as bfloat16.
+  // operator, lf.n = kept rows): t = r + F r.  jac = 0 writes t to out and,
+  // when part_rz is given, partial sums of t . t; jac = 1 writes z = sd1 * t
+  // and partial sums of r . z; jac = 2 does the same with z stored as
+  // bfloat16.  Partial-sum rows: elim_grid(lf.n).
   void (*elim_fwd)(const LevelArgs& lf, const void* r, void* out, const void* sd1, double* part_rz,
                    int jac, hipStream_t);
   // Elimination level, back substitution z_f = (r_f + sum_c w_fc z_c) / D_ff

@@ -1167,15 +1167,15 @@ __global__ __launch_bounds__(kBlock) void k_jl_rownorm(int n, const double* __re
 // which is symmetric whenever M_S is.
 
 // t = r + F r over the kept rows (F = the forward operator); with JAC the
-// next level is smoothed once in place: out = sd1 * t, partial sums r . out.
-// BF (with JAC): out is stored as bfloat16 and the partials use the rounded
-// values.
+// next level is smoothed once in place: out = sd1 * t, partial sums r . out;
+// without JAC, partial sums t . t when part is given.  BF (with JAC): out is
+// stored as bfloat16 and the partials use the rounded values.
 template <typename T, int W, bool JAC, bool BF>
 __global__ __launch_bounds__(kBlock) void k_elim_fwd(LevelArgs F, const T* __restrict__ r,
                                                      void* __restrict__ out, const T* __restrict__ sd1,
                                                      double* __restrict__ part) {
   constexpr int LPR = Shape<W>::LPR, V = Shape<W>::V, RG = Shape<W>::RG, WS = Shape<W>::WS;
-  __shared__ double lds[JAC ? RG * WS : 1];
+  __shared__ double lds[RG * WS];
   int slice, rb, grb;
   slice_of_block<W>(slice, rb, grb);
   const int rg = threadIdx.x / LPR, c0 = slice * WS + (threadIdx.x % LPR) * V;
@@ -1211,14 +1211,17 @@ __global__ __launch_bounds__(kBlock) void k_elim_fwd(LevelArgs F, const T* __res
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < V; ++i) ov.v[i] = ru.v[i] + nb[i];
+      for (int i = 0; i < V; ++i) {
+        ov.v[i] = ru.v[i] + nb[i];
+        acc[i] += double(ov.v[i]) * double(ov.v[i]);
+      }
     }
     if constexpr (BF)
       st<bf16_t, V>(static_cast<bf16_t*>(out) + o, oh);
     else
       st<T, V>(static_cast<T*>(out) + o, ov);
   }
-  if constexpr (JAC) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
+  if (JAC || part) block_store<W>(acc, lds, part + (size_t)rb * W + slice * WS);
 }
 
 // z_f for the eliminated rows, then partial sums of r . z over the eliminated

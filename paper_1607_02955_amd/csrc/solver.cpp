@@ -632,17 +632,16 @@ int Solver::pcg(const std::vector<double>& rr0, const std::vector<double>& itol,
   const DevLevel& fw = g->D->fwd;
   const int n = d0.n, nc = d0.nC;
   if (!w.rt.p) w.rt.alloc(g->ctx, (size_t)nc * w.W * (size_t)es);
-  k.elim_fwd(w.lf, w.ra.p, w.rt.p, nullptr, nullptr, 0, stream);
+  // the inner tolerance is relative to the folded residual, whose squared
+  // norms the fold kernel sums as it writes it
+  k.elim_fwd(w.lf, w.ra.p, w.rt.p, nullptr, w.part_ptr(P_RR), 0, stream);
   bytes += 2.0 * nc * w.W * es + (double)(n - nc) * w.W * es + 8.0 * fw.nnz + 4.0 * nc;
-  // the inner tolerance is relative to the folded residual
-  k.dot(nc, w.rt.p, w.rt.p, w.part_ptr(P_RR), stream);
-  finalize(w.W, F_R64, grid_for(nc, k.rg), w.part_ptr(P_RR), 0, nullptr, 0, nullptr, w.scal.as<double>(),
+  finalize(w.W, F_R64, k.elim_grid(nc), w.part_ptr(P_RR), 0, nullptr, 0, nullptr, w.scal.as<double>(),
            stream, w.mirror_dev);
   std::vector<double> rrt(w.W);
   read_scal(S_R64, rrt.data());
   for (int j = 0; j < w.W; ++j)
     if (!(rr0[j] > 0)) rrt[j] = 0;  // columns the caller left out stay out
-  bytes += nc * w.W * es;
   r0 = w.rt.p;
   const int it = pcg_iterations(rrt, itol, max_inner, check_every);
   if (xfu) {
